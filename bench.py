@@ -1,0 +1,183 @@
+"""VATE hot-path benchmark on one MI355X.
+
+One step = one 1 s time slice of the 40 Gb/s-shaped workload, the whole hot
+path: advance + two-block preservation, ingest of 5M packets (SetAT), pool
+census, and estimation of all 1M ANet hosts over the k = 60 slice window.
+Inputs (the packet stream and host list) are resident in HBM before the
+timed region starts.  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = ("packets/s AT update + hosts/s estimate on 1 GPU; "
+          "learned vs closed-form rel. error")
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(wl, pop, slices, budget_hosts: int = 20_000) -> dict:
+    """The CPU oracle, single-threaded, on a bounded sample of the same
+    workload: one slice of ingest (5M packets), the pool scan behind Z_p,
+    and the estimation of `budget_hosts` hosts, scaled to a whole slice
+    (all hosts), reported in packets/s."""
+    from oracle.vate_ref import OracleSketch, lib
+
+    ref = OracleSketch(wl.log2_pool, wl.width, wl.k, wl.g, 0xA5A5, 0x5A5A)
+    t0 = time.perf_counter()
+    ref.ingest(slices[0])
+    t_ingest = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    ref.close_slice()
+    t_close = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    ref.pool_inactive(wl.k)
+    t_scan = time.perf_counter() - t0
+    hosts = pop.aips[:budget_hosts]
+    t0 = time.perf_counter()
+    ref.estimate(hosts, want_live=False)
+    t_est = time.perf_counter() - t0
+    per_host = max(t_est - t_scan, 0.0) / hosts.size
+    # preservation of the two due blocks happens in the next close/ingest
+    t0 = time.perf_counter()
+    ref.close_slice()
+    t_adv = time.perf_counter() - t0
+    slice_s = t_ingest + t_close + t_scan + per_host * pop.n_hosts + t_adv
+    del lib
+    return {
+        "value": wl.packets_per_slice / slice_s,
+        "unit": "packets/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"one slice of the same stream: ingest {wl.packets_per_slice} packets, "
+                   f"one Z_p pool scan, estimate {hosts.size} of {pop.n_hosts} hosts "
+                   f"(scaled to all), one advance+preserve; "
+                   f"ingest {t_ingest:.2f}s, scan {t_scan:.2f}s, "
+                   f"{per_host * 1e6:.1f}us/host, advance {t_adv:.3f}s"),
+        "hosts_per_s": 1.0 / per_host if per_host > 0 else None,
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=60)
+    ap.add_argument("--warmup", type=int, default=4)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"),
+                    help="HBM traffic per estimate launch measured with rocprofv3 counters")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the VATE "
+              "path here is a single-GPU build.", file=sys.stderr)
+        return 2
+
+    import torch
+
+    from paper_1812_00282_amd import streams
+    from paper_1812_00282_amd.sketch import Config, Sketch
+
+    wl = streams.LINK40G
+    n_gen = min(wl.n_slices, args.warmup + args.steps)
+    log(f"[bench] generating {n_gen} slices of {wl.name}")
+    pop = wl.population()
+    host_slices = [wl.slice(pop, s) for s in range(n_gen)]
+    dev = torch.device("cuda:0")
+    slices = [torch.from_numpy(s.view(np.int32)).to(dev) for s in host_slices]
+    hosts = torch.from_numpy(pop.aips.view(np.int32)).to(dev)
+    cfg = Config(wl.log2_pool, wl.width, wl.k, wl.g, seed_a=0xA5A5, seed_b=0x5A5A)
+    sk = Sketch(cfg, device=dev)
+    est = torch.empty(pop.n_hosts, dtype=torch.float32, device=dev)
+    out = (est, None, None)
+    torch.cuda.synchronize()
+
+    def step(s, ev=None):
+        if ev is not None:
+            ev[0].record()
+        sk.ingest(slices[s % n_gen])        # advance + preserve, then SetAT
+        if ev is not None:
+            ev[1].record()
+        sk.close_slice()                    # census
+        if ev is not None:
+            ev[2].record()
+        sk.estimate(hosts, out=out)         # all hosts, k' = k
+        if ev is not None:
+            ev[3].record()
+
+    log(f"[bench] warmup {args.warmup}")
+    for s in range(args.warmup):
+        step(s)
+    torch.cuda.synchronize()
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    log(f"[bench] timing {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(args.warmup + i, events[i])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ingest_ms = np.mean([e[0].elapsed_time(e[1]) for e in events])
+    census_ms = np.mean([e[1].elapsed_time(e[2]) for e in events])
+    est_ms = np.mean([e[2].elapsed_time(e[3]) for e in events])
+    ms_per_step = elapsed * 1e3 / args.steps
+
+    # dominant kernel: the per-host estimate gather
+    bytes_per_host = 4 + wl.g * wl.width // 8 + 4
+    achieved = bytes_per_host * pop.n_hosts / (est_ms * 1e-3) / 1e9
+    traffic = None
+    if os.path.exists(args.traffic_json):
+        with open(args.traffic_json) as f:
+            tj = json.load(f)
+        traffic = tj.get("estimate_bytes_per_launch")
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                "kernel": "k_estimate<8,false>",
+                "algorithmic_bytes_per_launch": bytes_per_host * pop.n_hosts,
+                "avg_launch_ms": est_ms,
+                "random_lines_per_s": wl.g * pop.n_hosts / (est_ms * 1e-3)}
+
+    line = {
+        "metric": METRIC,
+        "value": wl.packets_per_slice * args.steps / elapsed,
+        "unit": "packets/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "packets_per_slice": wl.packets_per_slice,
+                   "hosts": pop.n_hosts, "log2_pool": wl.log2_pool, "width": wl.width,
+                   "k": wl.k, "kprime": wl.k, "g": wl.g, "slices_generated": n_gen},
+        "hosts_per_s": pop.n_hosts * args.steps / elapsed,
+        "phases_ms": {"advance_preserve_ingest": ingest_ms, "census": census_ms,
+                      "estimate": est_ms},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle)")
+        line["cpu_baseline"] = cpu_baseline(wl, pop, host_slices)
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -70,17 +70,27 @@ uint32_t o_fmix32(uint32_t h)
     return h;
 }
 
+uint32_t o_hash_BH(uint32_t g, uint32_t seed_b, uint32_t bip)
+{
+    uint64_t m = o_fmix32(bip ^ seed_b);
+    return (uint32_t)((m * (uint64_t)g) >> 32);
+}
+
+uint32_t o_hash_H(uint32_t c, uint32_t seed_a, uint32_t aip, uint32_t i)
+{
+    uint32_t x = o_fmix32(o_fmix32(aip ^ seed_a) ^ (uint32_t)(i * PHI));
+    /* floor(x * 2^c / 2^32) */
+    return (uint32_t)(((uint64_t)x << c) >> 32);
+}
+
 uint32_t o_BH(const o_vate *s, uint32_t bip)
 {
-    uint64_t m = o_fmix32(bip ^ s->seed_b);
-    return (uint32_t)((m * (uint64_t)s->g) >> 32);
+    return o_hash_BH(s->g, s->seed_b, bip);
 }
 
 uint32_t o_H(const o_vate *s, uint32_t aip, uint32_t i)
 {
-    uint32_t x = o_fmix32(o_fmix32(aip ^ s->seed_a) ^ (uint32_t)(i * PHI));
-    /* floor(x * 2^c / 2^32) */
-    return (uint32_t)(((uint64_t)x << s->c) >> 32);
+    return o_hash_H(s->c, s->seed_a, aip, i);
 }
 
 /* ---- AT blocks (Eq. 6-10, Fig. 4 / Fig. 5) ---- */

@@ -40,6 +40,8 @@ def lib():
         L = ctypes.CDLL(_LIB)
         sig = {
             "o_fmix32": (_u32, [_u32]),
+            "o_hash_BH": (_u32, [_u32, _u32, _u32]),
+            "o_hash_H": (_u32, [_u32, _u32, _u32, _u32]),
             "o_BH": (_u32, [_vp, _u32]),
             "o_H": (_u32, [_vp, _u32, _u32]),
             "o_block_of": (_u32, [_vp, _u64]),
@@ -80,6 +82,14 @@ def _ptr(a: np.ndarray) -> int:
 
 def fmix32(x: int) -> int:
     return lib().o_fmix32(x & 0xFFFFFFFF)
+
+
+def hash_BH(g: int, seed_b: int, bip: int) -> int:
+    return lib().o_hash_BH(g, seed_b & 0xFFFFFFFF, bip & 0xFFFFFFFF)
+
+
+def hash_H(c: int, seed_a: int, aip: int, i: int) -> int:
+    return lib().o_hash_H(c, seed_a & 0xFFFFFFFF, aip & 0xFFFFFFFF, i)
 
 
 def check_at(value: int, act: int, k: int, kprime: int) -> bool:

@@ -1,0 +1,768 @@
+// VATE hot path for MI355X (gfx950): pool init, packet ingest (SetAT),
+// pool census, per-host estimation, clock advance and two-block preservation,
+// behind the C ABI declared in include/vate.h.
+//
+// Paper: Xu, Ding, Hu, "VATE: a trade-off between memory and preserving time
+// for high accuracy cardinalities estimation under sliding time window",
+// arXiv 1812.00282.  Algorithm 4 is the per-slice loop; Sec. 4.2 describes
+// its three GPU phases (scan, estimate, maintain), which map to
+// k_ingest, k_census + k_estimate and k_advance + k_preserve here.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "vate.h"
+#include "vate_core.h"
+
+namespace vate {
+
+// ---------------------------------------------------------------------------
+// Device state block (caller-owned, 256-byte aligned).
+// ---------------------------------------------------------------------------
+struct DevState {
+    unsigned long long t;        // current slice
+    uint32_t bact0;              // ACT of block 0 (Eq. 7)
+    uint32_t pad0;
+    unsigned long long pad1[2];
+};
+constexpr size_t kStateHeader = sizeof(DevState);
+static_assert(kStateHeader == 32, "state header layout");
+
+// k counters follow the header: pool ATs whose distance is d < k.
+__host__ __device__ __forceinline__ unsigned long long *census_of(DevState *st)
+{
+    return reinterpret_cast<unsigned long long *>(st + 1);
+}
+__host__ __device__ __forceinline__ const unsigned long long *census_of(const DevState *st)
+{
+    return reinterpret_cast<const unsigned long long *>(st + 1);
+}
+constexpr int kMaxHistK = 256;      // per-host histogram limit (LDS budget)
+
+static size_t state_bytes_for(uint32_t k)
+{
+    size_t b = kStateHeader + 8ull * k;
+    return (b + 255) & ~size_t(255);
+}
+
+// ---------------------------------------------------------------------------
+// Parameter validation / geometry.
+// ---------------------------------------------------------------------------
+int make_geo(const vate_params *p, Geo *G, const char **why)
+{
+    if (!p) { *why = "params is NULL"; return VATE_E_INVAL; }
+    if (p->reserved != 0) { *why = "reserved must be 0"; return VATE_E_INVAL; }
+    if (p->log2_pool < 1 || p->log2_pool > 32) { *why = "log2_pool must be in [1, 32]"; return VATE_E_INVAL; }
+    if (p->width != 4 && p->width != 8 && p->width != 16) { *why = "width must be 4, 8 or 16"; return VATE_E_INVAL; }
+    if (p->k < 1) { *why = "k must be >= 1"; return VATE_E_INVAL; }
+    if ((1ull << p->width) < 2ull * p->k + 1) { *why = "width too small: need 2^width >= 2k+1"; return VATE_E_INVAL; }
+    if (p->g < 1 || p->g > 65535) { *why = "g must be in [1, 65535]"; return VATE_E_INVAL; }
+    if (p->partition > 1) { *why = "partition must be 0 or 1"; return VATE_E_INVAL; }
+    uint64_t N = 1ull << p->log2_pool;
+    if (N < 2ull * p->k) { *why = "pool smaller than 2k ATs"; return VATE_E_INVAL; }
+    if (N * p->width / 8 < 16) { *why = "pool smaller than 16 bytes"; return VATE_E_INVAL; }
+    Geo g{};
+    g.N = N;
+    g.c = p->log2_pool;
+    g.shift = 32 - p->log2_pool;
+    g.k = p->k;
+    g.twok = 2 * p->k;
+    g.g = p->g;
+    g.seed_a = p->seed_a;
+    g.seed_b = p->seed_b;
+    g.partition = p->partition;
+    const uint64_t E = 128 / p->width;   // ATs per 16-byte chunk
+    if (p->partition == 0) {
+        g.a = N / (g.twok - 1);
+        g.thresh = 0;
+        g.base1 = 0;
+        g.div_a = make_div32(g.a);
+        g.div_a1 = make_div32(1);
+        g.fast_blocks = g.a >= E;
+    } else {
+        uint64_t ap = N / g.twok, bp = N % g.twok;
+        g.a = ap;
+        g.base1 = (uint32_t)(g.twok - bp);
+        g.thresh = ap * (g.twok - bp);
+        g.div_a = make_div32(ap);
+        g.div_a1 = make_div32(ap + 1);
+        g.fast_blocks = ap >= E;
+    }
+    *G = g;
+    *why = "";
+    return VATE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Container access.  AT p sits at bits [p*W, p*W+W) of the pool, little-endian.
+// ---------------------------------------------------------------------------
+template <int W>
+__device__ __forceinline__ uint32_t load_at(const uint8_t *__restrict__ pool, uint32_t pid)
+{
+    if constexpr (W == 8) {
+        return pool[pid];
+    } else if constexpr (W == 16) {
+        return reinterpret_cast<const uint16_t *>(pool)[pid];
+    } else {
+        return (pool[pid >> 1] >> ((pid & 1u) << 2)) & 0xFu;
+    }
+}
+
+// Value e (0 <= e < 128/W) of a 16-byte chunk.
+template <int W>
+__device__ __forceinline__ uint32_t chunk_get(const uint4 &v, uint32_t e)
+{
+    constexpr uint32_t per_word = 32 / W;
+    uint32_t w = e / per_word, s = (e % per_word) * W;
+    uint32_t word = w == 0 ? v.x : w == 1 ? v.y : w == 2 ? v.z : v.w;
+    return (word >> s) & ((1u << W) - 1u);
+}
+
+template <int W>
+__device__ __forceinline__ void chunk_set(uint4 &v, uint32_t e, uint32_t val)
+{
+    constexpr uint32_t per_word = 32 / W;
+    uint32_t w = e / per_word, s = (e % per_word) * W;
+    uint32_t mask = ((1u << W) - 1u) << s;
+    uint32_t *word = w == 0 ? &v.x : w == 1 ? &v.y : w == 2 ? &v.z : &v.w;
+    *word = (*word & ~mask) | (val << s);
+}
+
+template <int W>
+__host__ __device__ __forceinline__ uint32_t replicate(uint32_t val)
+{
+    uint32_t r = 0;
+    for (int s = 0; s < 32; s += W) r |= val << s;
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// k_init: InitAT on every AT (value 2k), t = 0, BACT^0 = 0, census cleared.
+// ---------------------------------------------------------------------------
+template <int W>
+__global__ void __launch_bounds__(256) k_init(Geo G, uint4 *__restrict__ pool4, uint64_t nchunks,
+                                              DevState *__restrict__ st)
+{
+    const uint32_t pat = replicate<W>(G.twok);
+    const uint4 v = make_uint4(pat, pat, pat, pat);
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i < nchunks; i += (uint64_t)gridDim.x * blockDim.x) pool4[i] = v;
+    if (blockIdx.x == 0) {
+        if (threadIdx.x == 0) {
+            st->t = 0;
+            st->bact0 = 0;
+        }
+        for (uint32_t d = threadIdx.x; d < G.k; d += blockDim.x) census_of(st)[d] = 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_ingest: the scan phase.  Each thread takes 4 consecutive packets (two
+// 16-byte loads, so a wavefront reads 2 x 1 KiB contiguous), hashes them in
+// registers and stores the block ACT into the AT (SetAT).  Concurrent SetATs
+// of one AT in a slice all write the same value, so plain byte/short stores
+// are race-free; 4-bit ATs share a 32-bit word with a neighbour and are
+// written with an atomic OR of the set bits then an atomic AND of the clear
+// bits, which leaves the nibble equal to ACT whatever the interleaving.
+// ---------------------------------------------------------------------------
+template <int W>
+__device__ __forceinline__ void set_at(uint8_t *__restrict__ pool, uint32_t pid, uint32_t act)
+{
+    if constexpr (W == 8) {
+        pool[pid] = (uint8_t)act;
+    } else if constexpr (W == 16) {
+        reinterpret_cast<uint16_t *>(pool)[pid] = (uint16_t)act;
+    } else {
+        uint32_t *w32 = reinterpret_cast<uint32_t *>(pool) + (pid >> 3);
+        uint32_t s = (pid & 7u) << 2;
+        atomicOr(w32, act << s);
+        atomicAnd(w32, ~((~act & 0xFu) << s));
+    }
+}
+
+template <int W>
+__device__ __forceinline__ void ingest_one(const Geo &G, uint8_t *__restrict__ pool, uint32_t bact0,
+                                           uint32_t aip, uint32_t bip)
+{
+    uint32_t vid = bh(G, bip);
+    uint32_t pid = vat_pid(G, host_key(G, aip), vid);
+    uint32_t act = block_act(G, bact0, block_of(G, pid));
+    set_at<W>(pool, pid, act);
+}
+
+template <int W, bool ALIGNED16>
+__global__ void __launch_bounds__(256) k_ingest(Geo G, const uint32_t *__restrict__ pairs, uint64_t n,
+                                                uint8_t *__restrict__ pool, const DevState *__restrict__ st)
+{
+    const uint32_t bact0 = st->bact0;
+    const uint64_t base = (uint64_t)blockIdx.x * 1024;   // packets per block
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+        const uint64_t j = base + (uint64_t)half * 512 + 2ull * threadIdx.x;   // first of 2 packets
+        if (ALIGNED16 && j + 2 <= n) {
+            uint4 v = reinterpret_cast<const uint4 *>(pairs)[j >> 1];
+            ingest_one<W>(G, pool, bact0, v.x, v.y);
+            ingest_one<W>(G, pool, bact0, v.z, v.w);
+        } else {
+            for (uint64_t q = j; q < j + 2 && q < n; ++q) {
+                uint2 v = reinterpret_cast<const uint2 *>(pairs)[q];
+                ingest_one<W>(G, pool, bact0, v.x, v.y);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_census: one streaming pass over the pool at the end of a slice.  Builds
+// the histogram of AT distances d < k (Eq. 5) with per-workgroup LDS counters
+// flushed by 64-bit atomics; Z_p for any k' is then N minus a prefix sum.
+// In steady state most ATs hold 2k, so 16-byte chunks that are entirely
+// inactive are skipped after one compare.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kCensusLdsBins = 4096;
+
+template <int W>
+__global__ void __launch_bounds__(256) k_census(Geo G, const uint4 *__restrict__ pool4, uint64_t nchunks,
+                                                DevState *__restrict__ st)
+{
+    __shared__ uint32_t hist[kCensusLdsBins];
+    const bool lds = G.k <= kCensusLdsBins;
+    if (lds)
+        for (uint32_t d = threadIdx.x; d < G.k; d += blockDim.x) hist[d] = 0;
+    __syncthreads();
+    const uint32_t bact0 = st->bact0;
+    const uint32_t pat = replicate<W>(G.twok);
+    constexpr uint32_t E = 128 / W;
+    constexpr int U = 4;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t c0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c0 < nchunks; c0 += U * stride) {
+        uint4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            uint64_t ch = c0 + u * stride;
+            v[u] = ch < nchunks ? pool4[ch] : make_uint4(pat, pat, pat, pat);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (v[u].x == pat && v[u].y == pat && v[u].z == pat && v[u].w == pat) continue;
+            const uint64_t p0 = (c0 + u * stride) * E;
+            uint32_t bid0 = 0, act0 = 0;
+            uint64_t next = 0;
+            if (G.fast_blocks) {
+                bid0 = block_of(G, (uint32_t)p0);
+                act0 = block_act(G, bact0, bid0);
+                next = block_start(G, bid0 + 1);
+            }
+            for (uint32_t e = 0; e < E; ++e) {
+                uint32_t val = chunk_get<W>(v[u], e);
+                if (val == G.twok) continue;
+                uint32_t act;
+                if (G.fast_blocks)
+                    act = p0 + e < next ? act0 : block_act(G, bact0, bid0 + 1);
+                else
+                    act = block_act(G, bact0, block_of(G, (uint32_t)(p0 + e)));
+                uint32_t d = at_dist(G, act, val);
+                if (d < G.k) {
+                    if (lds) atomicAdd(&hist[d], 1u);
+                    else atomicAdd(&census_of(st)[d], 1ull);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (lds)
+        for (uint32_t d = threadIdx.x; d < G.k; d += blockDim.x)
+            if (hist[d]) atomicAdd(&census_of(st)[d], (unsigned long long)hist[d]);
+}
+
+// ---------------------------------------------------------------------------
+// k_estimate: one thread per host.  The g VATs of the host are gathered in
+// batches of U independent byte loads (U gathers of 64 random lines in flight
+// per wavefront), decoded with CheckAT (Alg. 1), counted, and the estimate
+// of Eq. 11 is formed in FP32 from exact integer counts.  With HIST each
+// lane also keeps the host's distance histogram in LDS as pairs of 16-bit
+// counters in lane-private columns (conflict-free increments), written out
+// transposed so that the (hosts x (k+1)) output is stored contiguously.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float estimate_from_counts(uint64_t u_v, uint64_t u_p, uint32_t g, uint32_t c)
+{
+    if (u_v == 0) u_v = 1;
+    if (u_p == 0) u_p = 1;
+    const uint64_t N = 1ull << c;
+    const long long D = (long long)(u_p * g) - (long long)(N * u_v);
+    const float den = ldexpf((float)u_v, (int)c);          // N * u_v, exact
+    const float x = (float)D / den;
+    if (x >= -0.5f)
+        return (float)g * log1pf(x);
+    return (float)g * logf((float)(u_p * g) / den);
+}
+
+// Number of pool ATs active for k' (sum of census bins d < k'), per wavefront.
+__device__ __forceinline__ uint64_t pool_active(const DevState *__restrict__ st, uint32_t kprime)
+{
+    const uint32_t lane = threadIdx.x & 63u;
+    unsigned long long s = 0;
+    for (uint32_t d = lane; d < kprime; d += 64) s += census_of(st)[d];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    return s;
+}
+
+constexpr int kEstU = 16;   // VAT gathers in flight per thread
+
+template <int W, bool HIST>
+__global__ void __launch_bounds__(256) k_estimate(Geo G, const uint8_t *__restrict__ pool,
+                                                  const DevState *__restrict__ st,
+                                                  const uint32_t *__restrict__ hosts, uint32_t n,
+                                                  uint32_t kprime, float *__restrict__ est,
+                                                  uint32_t *__restrict__ live_out,
+                                                  uint32_t *__restrict__ hist_out)
+{
+    extern __shared__ uint32_t lds_hist[];   // HIST: [waves][rows + 1][65]
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+    const uint32_t rows = (G.k + 1) / 2;     // bins d and d^1 share a dword
+    uint32_t *my = lds_hist + (size_t)wave * (rows + 1) * 65;
+    if (HIST) {
+        for (uint32_t r = 0; r < rows; ++r) my[r * 65 + lane] = 0;
+    }
+    const uint64_t active_pool = pool_active(st, kprime);
+    const uint32_t bact0 = st->bact0;
+    const uint32_t h = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = h < n;
+    const uint32_t key = host_key(G, valid ? hosts[h] : 0u);
+    uint32_t live = 0, live_k = 0;
+    for (uint32_t i0 = 0; i0 < G.g; i0 += kEstU) {
+        uint32_t pid[kEstU], val[kEstU];
+#pragma unroll
+        for (int u = 0; u < kEstU; ++u) pid[u] = vat_pid(G, key, i0 + u);
+#pragma unroll
+        for (int u = 0; u < kEstU; ++u)
+            val[u] = (valid && i0 + u < G.g) ? load_at<W>(pool, pid[u]) : G.twok;
+#pragma unroll
+        for (int u = 0; u < kEstU; ++u) {
+            if (val[u] == G.twok) continue;
+            const uint32_t act = block_act(G, bact0, block_of(G, pid[u]));
+            const uint32_t d = at_dist(G, act, val[u]);
+            live += d < kprime;
+            if (HIST && d < G.k) {
+                ++live_k;
+                atomicAdd(&my[(d >> 1) * 65 + lane], 1u << ((d & 1u) << 4));
+            }
+        }
+    }
+    if (valid) {
+        est[h] = estimate_from_counts(G.g - live, G.N - active_pool, G.g, G.c);
+        if (live_out) live_out[h] = live;
+    }
+    if (HIST) {
+        my[rows * 65 + lane] = live_k;
+        __syncthreads();
+        const uint32_t h0 = blockIdx.x * blockDim.x + wave * 64;
+        if (h0 < n) {
+            const uint32_t nh = min(64u, n - h0), kp1 = G.k + 1;
+            uint32_t *out = hist_out + (size_t)h0 * kp1;
+            for (uint32_t e = lane; e < nh * kp1; e += 64) {
+                const uint32_t host = e / kp1, bin = e - host * kp1;
+                uint32_t v;
+                if (bin < G.k)
+                    v = (my[(bin >> 1) * 65 + host] >> ((bin & 1u) << 4)) & 0xFFFFu;
+                else
+                    v = G.g - my[rows * 65 + host];
+                out[e] = v;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Slice advance: BACT^0 = (BACT^0 + 1) mod 2k, t = t + 1 (Alg. 4 end of loop),
+// census cleared for the new slice.
+// ---------------------------------------------------------------------------
+__global__ void k_advance(Geo G, DevState *__restrict__ st)
+{
+    if (threadIdx.x == 0) {
+        st->bact0 = st->bact0 + 1 == G.twok ? 0 : st->bact0 + 1;
+        st->t = st->t + 1;
+    }
+    for (uint32_t d = threadIdx.x; d < G.k; d += blockDim.x) census_of(st)[d] = 0;
+}
+
+__global__ void k_set_clock(Geo G, DevState *__restrict__ st, unsigned long long t, uint32_t bact0)
+{
+    if (threadIdx.x == 0) {
+        st->t = t;
+        st->bact0 = bact0;
+    }
+    for (uint32_t d = threadIdx.x; d < G.k; d += blockDim.x) census_of(st)[d] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// k_preserve: PreserveAT (Alg. 3) over the two blocks whose ACT is now 0
+// (block i0) or k (block i1), Cor. 1.  Block indices come from the device
+// clock so a captured graph replays correctly.  Each 16-byte chunk that
+// overlaps a due block is owned by exactly one thread (a chunk shared by both
+// blocks belongs to the i0 pass), which rewrites it only if an AT changed.
+// ---------------------------------------------------------------------------
+template <int W>
+__global__ void __launch_bounds__(256) k_preserve(Geo G, uint4 *__restrict__ pool4,
+                                                  const DevState *__restrict__ st, uint64_t max_chunks)
+{
+    constexpr uint64_t E = 128 / W;
+    const uint32_t bact0 = st->bact0;
+    const uint32_t i0 = bact0 == 0 ? 0 : G.twok - bact0;                        // (BACT^0 + i0) mod 2k == 0
+    const uint32_t i1 = bact0 <= G.k ? G.k - bact0 : G.twok + G.k - bact0;      // == k
+    const uint64_t s0 = block_start(G, i0), e0 = block_start(G, i0 + 1);
+    const uint64_t s1 = block_start(G, i1), e1 = block_start(G, i1 + 1);
+    const uint64_t c0lo = s0 / E, c0hi = s0 < e0 ? (e0 + E - 1) / E : c0lo;
+    const uint64_t c1lo = s1 / E, c1hi = s1 < e1 ? (e1 + E - 1) / E : c1lo;
+    const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool second = j >= max_chunks;
+    const uint64_t ch = second ? c1lo + (j - max_chunks) : c0lo + j;
+    if (j >= 2 * max_chunks) return;
+    if (ch >= (second ? c1hi : c0hi)) return;
+    if (second && ch >= c0lo && ch < c0hi) return;
+    uint4 v = pool4[ch];
+    bool changed = false;
+    for (uint32_t e = 0; e < E; ++e) {
+        const uint64_t p = ch * E + e;
+        const bool in0 = p >= s0 && p < e0, in1 = p >= s1 && p < e1;
+        if (!in0 && !in1) continue;
+        const uint32_t val = chunk_get<W>(v, e);
+        bool mark;
+        if (in0)   // ACT == 0: 0 <= Value <= k
+            mark = val <= G.k;
+        else       // ACT == k: k <= Value <= 2k-1, or Value == 0
+            mark = (val >= G.k && val <= G.twok - 1) || val == 0;
+        if (mark && val != G.twok) {
+            chunk_set<W>(v, e, G.twok);
+            changed = true;
+        }
+    }
+    if (changed) pool4[ch] = v;
+}
+
+}  // namespace vate
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+using namespace vate;
+
+struct vate_sketch {
+    vate_params p;
+    Geo G;
+    uint8_t *pool;
+    DevState *st;
+    size_t pool_bytes, state_bytes;
+    uint64_t max_block_chunks;   // chunks a due block can overlap
+    int closed;                  // 1: slice ended, estimates allowed
+    int dead;                    // sticky device error
+    char err[256];
+};
+
+static int fail(vate_sketch *s, int code, const char *msg)
+{
+    if (s) {
+        snprintf(s->err, sizeof(s->err), "%s", msg);
+        if (code == VATE_E_DEVICE) s->dead = 1;
+    }
+    return code;
+}
+
+static int check_launch(vate_sketch *s, const char *what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        char buf[200];
+        snprintf(buf, sizeof(buf), "%s: %s", what, hipGetErrorString(e));
+        return fail(s, VATE_E_DEVICE, buf);
+    }
+    return VATE_OK;
+}
+
+static unsigned grid_for(uint64_t items, unsigned per_block, unsigned cap)
+{
+    uint64_t b = (items + per_block - 1) / per_block;
+    if (b < 1) b = 1;
+    return (unsigned)std::min<uint64_t>(b, cap);
+}
+
+template <int W>
+static void launch_init(vate_sketch *s, hipStream_t st)
+{
+    uint64_t nch = s->pool_bytes / 16;
+    k_init<W><<<grid_for(nch, 256, 8192), 256, 0, st>>>(s->G, reinterpret_cast<uint4 *>(s->pool), nch, s->st);
+}
+
+template <int W>
+static void launch_census(vate_sketch *s, hipStream_t st)
+{
+    uint64_t nch = s->pool_bytes / 16;
+    k_census<W><<<grid_for(nch, 256 * 4, 4096), 256, 0, st>>>(s->G, reinterpret_cast<const uint4 *>(s->pool),
+                                                               nch, s->st);
+}
+
+template <int W>
+static void launch_preserve(vate_sketch *s, hipStream_t st)
+{
+    uint64_t threads = 2 * s->max_block_chunks;
+    k_preserve<W><<<grid_for(threads, 256, 1u << 30), 256, 0, st>>>(s->G, reinterpret_cast<uint4 *>(s->pool),
+                                                                     s->st, s->max_block_chunks);
+}
+
+template <int W>
+static void launch_ingest(vate_sketch *s, const uint32_t *pairs, uint64_t n, hipStream_t st)
+{
+    unsigned blocks = grid_for(n, 1024, 1u << 30);
+    if ((reinterpret_cast<uintptr_t>(pairs) & 15u) == 0)
+        k_ingest<W, true><<<blocks, 256, 0, st>>>(s->G, pairs, n, s->pool, s->st);
+    else
+        k_ingest<W, false><<<blocks, 256, 0, st>>>(s->G, pairs, n, s->pool, s->st);
+}
+
+static void dispatch_init(vate_sketch *s, hipStream_t st)
+{
+    if (s->p.width == 4) launch_init<4>(s, st);
+    else if (s->p.width == 8) launch_init<8>(s, st);
+    else launch_init<16>(s, st);
+}
+
+static void dispatch_census(vate_sketch *s, hipStream_t st)
+{
+    if (s->p.width == 4) launch_census<4>(s, st);
+    else if (s->p.width == 8) launch_census<8>(s, st);
+    else launch_census<16>(s, st);
+}
+
+static int advance(vate_sketch *s, hipStream_t st)
+{
+    k_advance<<<1, 256, 0, st>>>(s->G, s->st);
+    if (s->p.width == 4) launch_preserve<4>(s, st);
+    else if (s->p.width == 8) launch_preserve<8>(s, st);
+    else launch_preserve<16>(s, st);
+    s->closed = 0;
+    return check_launch(s, "advance/preserve");
+}
+
+template <int W>
+static void launch_estimate(vate_sketch *s, const uint32_t *hosts, uint32_t n, uint32_t kprime, float *est,
+                            uint32_t *live, uint32_t *hist, hipStream_t st)
+{
+    if (hist) {
+        const uint32_t k = s->G.k;
+        const unsigned threads = k <= 64 ? 256 : k <= 128 ? 128 : 64;
+        const size_t lds = (size_t)(threads / 64) * ((k + 1) / 2 + 1) * 65 * sizeof(uint32_t);
+        k_estimate<W, true><<<grid_for(n, threads, 1u << 30), threads, lds, st>>>(s->G, s->pool, s->st, hosts, n,
+                                                                                  kprime, est, live, hist);
+    } else {
+        k_estimate<W, false><<<grid_for(n, 256, 1u << 30), 256, 0, st>>>(s->G, s->pool, s->st, hosts, n, kprime,
+                                                                         est, live, nullptr);
+    }
+}
+
+extern "C" {
+
+int vate_state_bytes(const vate_params *p, size_t *pool_bytes, size_t *state_bytes)
+{
+    Geo G;
+    const char *why;
+    int rc = make_geo(p, &G, &why);
+    if (rc != VATE_OK) return rc;
+    if (pool_bytes) *pool_bytes = (size_t)(G.N * p->width / 8);
+    if (state_bytes) *state_bytes = state_bytes_for(p->k);
+    return VATE_OK;
+}
+
+int vate_create(const vate_params *p, void *pool_dev, void *state_dev, void *stream, vate_sketch **out)
+{
+    if (!out) return VATE_E_INVAL;
+    *out = nullptr;
+    Geo G;
+    const char *why;
+    int rc = make_geo(p, &G, &why);
+    if (rc != VATE_OK) return rc;
+    if (!pool_dev || !state_dev) return VATE_E_INVAL;
+    if ((reinterpret_cast<uintptr_t>(pool_dev) & 255u) || (reinterpret_cast<uintptr_t>(state_dev) & 255u))
+        return VATE_E_INVAL;
+    vate_sketch *s = new (std::nothrow) vate_sketch();
+    if (!s) return VATE_E_NOMEM;
+    s->p = *p;
+    s->G = G;
+    s->pool = static_cast<uint8_t *>(pool_dev);
+    s->st = static_cast<DevState *>(state_dev);
+    s->pool_bytes = (size_t)(G.N * p->width / 8);
+    s->state_bytes = state_bytes_for(p->k);
+    uint64_t maxb = 0;
+    for (uint32_t i = 0; i < G.twok; ++i)
+        maxb = std::max<uint64_t>(maxb, block_start(G, i + 1) - block_start(G, i));
+    const uint64_t E = 128 / p->width;
+    s->max_block_chunks = (maxb + E - 1) / E + 1;
+    s->closed = 0;
+    s->dead = 0;
+    s->err[0] = 0;
+    dispatch_init(s, static_cast<hipStream_t>(stream));
+    rc = check_launch(s, "init");
+    if (rc != VATE_OK) {
+        delete s;
+        return rc;
+    }
+    *out = s;
+    return VATE_OK;
+}
+
+int vate_ingest(vate_sketch *s, const uint32_t *pairs_dev, size_t n, void *stream)
+{
+    if (!s) return VATE_E_INVAL;
+    if (s->dead) return VATE_E_DEVICE;
+    if (n > 0 && (!pairs_dev || (reinterpret_cast<uintptr_t>(pairs_dev) & 7u)))
+        return fail(s, VATE_E_INVAL, "pairs must be non-NULL and 8-byte aligned");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (s->closed) {
+        int rc = advance(s, st);
+        if (rc != VATE_OK) return rc;
+    }
+    if (n == 0) return VATE_OK;
+    if (s->p.width == 4) launch_ingest<4>(s, pairs_dev, n, st);
+    else if (s->p.width == 8) launch_ingest<8>(s, pairs_dev, n, st);
+    else launch_ingest<16>(s, pairs_dev, n, st);
+    return check_launch(s, "ingest");
+}
+
+int vate_close_slice(vate_sketch *s, void *stream)
+{
+    if (!s) return VATE_E_INVAL;
+    if (s->dead) return VATE_E_DEVICE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (s->closed) {
+        int rc = advance(s, st);
+        if (rc != VATE_OK) return rc;
+    }
+    dispatch_census(s, st);
+    int rc = check_launch(s, "census");
+    if (rc != VATE_OK) return rc;
+    s->closed = 1;
+    return VATE_OK;
+}
+
+int vate_estimate(vate_sketch *s, const uint32_t *hosts_dev, size_t n_hosts, uint32_t kprime, float *est_dev,
+                  uint32_t *live_dev, uint32_t *hist_dev, void *stream)
+{
+    if (!s) return VATE_E_INVAL;
+    if (s->dead) return VATE_E_DEVICE;
+    if (!s->closed) return fail(s, VATE_E_STATE, "estimate needs a closed slice (call vate_close_slice)");
+    if (kprime < 1 || kprime > s->p.k) return fail(s, VATE_E_INVAL, "k' must be in [1, k]");
+    if (n_hosts > 0xFFFFFFFFull - 1024) return fail(s, VATE_E_INVAL, "too many hosts");
+    if (hist_dev && s->p.k > (uint32_t)kMaxHistK)
+        return fail(s, VATE_E_UNSUPPORTED, "per-host histogram needs k <= 256");
+    if (n_hosts == 0) return VATE_OK;
+    if (!hosts_dev || !est_dev || (reinterpret_cast<uintptr_t>(hosts_dev) & 3u) ||
+        (reinterpret_cast<uintptr_t>(est_dev) & 3u) || (reinterpret_cast<uintptr_t>(live_dev) & 3u) ||
+        (reinterpret_cast<uintptr_t>(hist_dev) & 3u))
+        return fail(s, VATE_E_INVAL, "hosts/est/live/hist must be non-NULL (live, hist may be NULL) and 4-byte aligned");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const uint32_t n = (uint32_t)n_hosts;
+    if (s->p.width == 4) launch_estimate<4>(s, hosts_dev, n, kprime, est_dev, live_dev, hist_dev, st);
+    else if (s->p.width == 8) launch_estimate<8>(s, hosts_dev, n, kprime, est_dev, live_dev, hist_dev, st);
+    else launch_estimate<16>(s, hosts_dev, n, kprime, est_dev, live_dev, hist_dev, st);
+    return check_launch(s, "estimate");
+}
+
+int vate_read_census(vate_sketch *s, uint64_t *census_host, void *stream)
+{
+    if (!s || !census_host) return VATE_E_INVAL;
+    if (s->dead) return VATE_E_DEVICE;
+    if (!s->closed) return fail(s, VATE_E_STATE, "census needs a closed slice");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e = hipStreamSynchronize(st);
+    if (e == hipSuccess)
+        e = hipMemcpy(census_host, census_of(s->st), 8ull * s->p.k, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return fail(s, VATE_E_DEVICE, hipGetErrorString(e));
+    uint64_t act = 0;
+    for (uint32_t d = 0; d < s->p.k; ++d) act += census_host[d];
+    census_host[s->p.k] = s->G.N - act;
+    return VATE_OK;
+}
+
+int vate_read_state(vate_sketch *s, void *pool_dst, uint64_t *t, uint32_t *bact0, int *closed, void *stream)
+{
+    if (!s) return VATE_E_INVAL;
+    if (s->dead) return VATE_E_DEVICE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e = hipStreamSynchronize(st);
+    DevState hdr;
+    if (e == hipSuccess && pool_dst) e = hipMemcpy(pool_dst, s->pool, s->pool_bytes, hipMemcpyDefault);
+    if (e == hipSuccess) e = hipMemcpy(&hdr, s->st, kStateHeader, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return fail(s, VATE_E_DEVICE, hipGetErrorString(e));
+    if (t) *t = hdr.t;
+    if (bact0) *bact0 = hdr.bact0;
+    if (closed) *closed = s->closed;
+    return VATE_OK;
+}
+
+int vate_load_state(vate_sketch *s, const void *pool_src, uint64_t t, uint32_t bact0, int closed, void *stream)
+{
+    if (!s || !pool_src) return VATE_E_INVAL;
+    if (s->dead) return VATE_E_DEVICE;
+    if (bact0 >= s->G.twok) return fail(s, VATE_E_INVAL, "bact0 must be < 2k");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e = hipMemcpyAsync(s->pool, pool_src, s->pool_bytes, hipMemcpyDefault, st);
+    if (e != hipSuccess) return fail(s, VATE_E_DEVICE, hipGetErrorString(e));
+    k_set_clock<<<1, 256, 0, st>>>(s->G, s->st, (unsigned long long)t, bact0);
+    int rc = check_launch(s, "load_state");
+    if (rc != VATE_OK) return rc;
+    s->closed = 0;
+    if (closed) {
+        dispatch_census(s, st);
+        rc = check_launch(s, "census");
+        if (rc != VATE_OK) return rc;
+        s->closed = 1;
+    }
+    return VATE_OK;
+}
+
+const char *vate_last_error(const vate_sketch *s)
+{
+    return s ? s->err : "";
+}
+
+const char *vate_status_string(int code)
+{
+    switch (code) {
+    case VATE_OK: return "ok";
+    case VATE_E_INVAL: return "invalid argument";
+    case VATE_E_STATE: return "call not allowed in the current slice phase";
+    case VATE_E_DEVICE: return "HIP device error";
+    case VATE_E_NOMEM: return "out of host memory";
+    case VATE_E_UNSUPPORTED: return "unsupported request";
+    default: return "unknown status";
+    }
+}
+
+void vate_destroy(vate_sketch *s)
+{
+    delete s;
+}
+
+uint32_t vate_host_hash(const vate_params *p, uint32_t which, uint32_t x, uint32_t i)
+{
+    Geo G;
+    const char *why;
+    if (make_geo(p, &G, &why) != VATE_OK) return 0xFFFFFFFFu;
+    if (which == 0) return bh(G, x);
+    if (which == 1) return vat_pid(G, host_key(G, x), i);
+    return 0xFFFFFFFFu;
+}
+
+uint32_t vate_host_block(const vate_params *p, uint64_t pid)
+{
+    Geo G;
+    const char *why;
+    if (make_geo(p, &G, &why) != VATE_OK || pid >= G.N) return 0xFFFFFFFFu;
+    return block_of(G, (uint32_t)pid);
+}
+
+}  // extern "C"

@@ -1,0 +1,139 @@
+"""Python face of one VATE sketch on the GPU.
+
+PyTorch provides the device memory (pool, state, inputs, outputs) and the
+stream; the library's kernels do the work.  Tensors holding 32-bit IDs are
+int32 tensors whose bits are the unsigned values.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import VateParams, check, lib
+
+
+def _stream_handle(stream: torch.cuda.Stream | None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def as_u32_tensor(x, device) -> torch.Tensor:
+    """uint32 numpy array / int32 tensor -> contiguous int32 tensor on device."""
+    if isinstance(x, np.ndarray):
+        x = torch.from_numpy(np.ascontiguousarray(x, dtype=np.uint32).view(np.int32))
+    if x.dtype != torch.int32:
+        raise TypeError("expected uint32 numpy data or an int32 tensor")
+    return x.to(device, non_blocking=True).contiguous()
+
+
+@dataclass(frozen=True)
+class Config:
+    log2_pool: int
+    width: int
+    k: int
+    g: int
+    partition: int = 0
+    seed_a: int = 0
+    seed_b: int = 0
+
+    def params(self) -> VateParams:
+        return VateParams(self.log2_pool, self.width, self.k, self.g, self.partition,
+                          self.seed_a & 0xFFFFFFFF, self.seed_b & 0xFFFFFFFF, 0)
+
+
+def state_bytes(cfg: Config) -> tuple[int, int]:
+    pb, sb = ctypes.c_size_t(), ctypes.c_size_t()
+    p = cfg.params()
+    check(lib().vate_state_bytes(ctypes.byref(p), ctypes.byref(pb), ctypes.byref(sb)))
+    return pb.value, sb.value
+
+
+class Sketch:
+    """One VATE sketch: ingest* -> close_slice -> estimate* per time slice."""
+
+    def __init__(self, cfg: Config, device="cuda", stream: torch.cuda.Stream | None = None):
+        self.cfg = cfg
+        self.device = torch.device(device)
+        self.pool_bytes, self.state_bytes = state_bytes(cfg)
+        self.pool = torch.empty(self.pool_bytes, dtype=torch.uint8, device=self.device)
+        self.state = torch.empty(self.state_bytes, dtype=torch.uint8, device=self.device)
+        self._p = cfg.params()
+        h = ctypes.c_void_p()
+        check(lib().vate_create(ctypes.byref(self._p), self.pool.data_ptr(), self.state.data_ptr(),
+                                _stream_handle(stream), ctypes.byref(h)))
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().vate_destroy(h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def ingest(self, pairs, stream=None) -> None:
+        """pairs: (n, 2) uint32 (aip, bip) as numpy or int32 tensor."""
+        t = as_u32_tensor(pairs, self.device).reshape(-1)
+        n = t.numel() // 2
+        check(lib().vate_ingest(self._h, t.data_ptr() if n else None, n, _stream_handle(stream)),
+              self._h)
+        self._keep = t          # keep the input alive until the stream reaches it
+
+    def close_slice(self, stream=None) -> None:
+        check(lib().vate_close_slice(self._h, _stream_handle(stream)), self._h)
+
+    def estimate(self, hosts, kprime: int | None = None, want_live: bool = True,
+                 want_hist: bool = False, stream=None, out=None):
+        """Returns (est float32, live int32 or None, hist int32 (n, k+1) or None)."""
+        ht = as_u32_tensor(hosts, self.device)
+        n = ht.numel()
+        kp = self.cfg.k if kprime is None else kprime
+        if out is not None:
+            est, live, hist = out
+        else:
+            est = torch.empty(n, dtype=torch.float32, device=self.device)
+            live = torch.empty(n, dtype=torch.int32, device=self.device) if want_live else None
+            hist = (torch.empty((n, self.cfg.k + 1), dtype=torch.int32, device=self.device)
+                    if want_hist else None)
+        check(lib().vate_estimate(self._h, ht.data_ptr() if n else None, n, kp,
+                                  est.data_ptr() if n else None,
+                                  live.data_ptr() if (live is not None and n) else None,
+                                  hist.data_ptr() if (hist is not None and n) else None,
+                                  _stream_handle(stream)), self._h)
+        self._keep_h = ht
+        return est, live, hist
+
+    def census(self, stream=None) -> np.ndarray:
+        out = np.zeros(self.cfg.k + 1, dtype=np.uint64)
+        check(lib().vate_read_census(self._h, out.ctypes.data, _stream_handle(stream)), self._h)
+        return out
+
+    def read_state(self, stream=None):
+        """(pool bytes as numpy uint8, t, bact0, closed)."""
+        pool = np.empty(self.pool_bytes, dtype=np.uint8)
+        t, b, c = ctypes.c_uint64(), ctypes.c_uint32(), ctypes.c_int()
+        check(lib().vate_read_state(self._h, pool.ctypes.data, ctypes.byref(t), ctypes.byref(b),
+                                    ctypes.byref(c), _stream_handle(stream)), self._h)
+        return pool, t.value, b.value, bool(c.value)
+
+    def load_state(self, pool: np.ndarray, t: int, bact0: int, closed: bool, stream=None) -> None:
+        src = torch.from_numpy(np.ascontiguousarray(pool, dtype=np.uint8)).to(self.device)
+        check(lib().vate_load_state(self._h, src.data_ptr(), t, bact0, int(closed),
+                                    _stream_handle(stream)), self._h)
+        self._keep_pool = src
+
+
+def host_hash(cfg: Config, which: int, x: int, i: int = 0) -> int:
+    p = cfg.params()
+    return lib().vate_host_hash(ctypes.byref(p), which, x & 0xFFFFFFFF, i)
+
+
+def host_block(cfg: Config, pid: int) -> int:
+    p = cfg.params()
+    return lib().vate_host_block(ctypes.byref(p), pid)

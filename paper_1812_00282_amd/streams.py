@@ -12,7 +12,9 @@ slice for a 40 Gb/s link.
 
 A population is a set of ANet hosts (distinct uniform 32-bit aips), each with
 a universe of n_h opposite hosts (uniform 32-bit bips) and an activity weight.
-A slice draws P packets: host by weight, bip uniform from the host's universe.
+A slice draws P packets: per-host packet counts from a multinomial over the
+activity weights, shuffled, and each packet's bip uniform from its host's
+universe.
 Slice s of a stream is generated from its own child seed, so any slice can be
 produced independently of the others.
 """
@@ -36,7 +38,7 @@ def _distinct_u32(rng: np.random.Generator, n: int) -> np.ndarray:
 class Population:
     aips: np.ndarray        # (H,) uint32 distinct host ids
     card: np.ndarray        # (H,) int64 universe size n_h
-    weight_cdf: np.ndarray  # (H,) float64 cumulative activity weights, last = 1
+    weight: np.ndarray      # (H,) float64 activity probabilities, sum 1
     universe: np.ndarray    # (sum n_h,) uint32 opposite hosts, host-major
     offset: np.ndarray      # (H,) int64 start of each host's universe
 
@@ -64,19 +66,19 @@ def make_population(seed: int, n_hosts: int, alpha: float, card_max: int,
         w = ranks ** (-zipf_s)
     else:
         raise ValueError(activity)
-    cdf = np.cumsum(w)
-    cdf /= cdf[-1]
+    w = w / w.sum()
     offset = np.zeros(n_hosts, dtype=np.int64)
     np.cumsum(card[:-1], out=offset[1:])
     universe = rng.integers(0, 2**32, size=int(card.sum()), dtype=np.uint64).astype(np.uint32)
-    return Population(aips, card, cdf, universe, offset)
+    return Population(aips, card, w, universe, offset)
 
 
 def draw_slice(pop: Population, seed: int, s: int, n_packets: int) -> np.ndarray:
     """(n_packets, 2) uint32 array of (aip, bip) pairs for slice s."""
     rng = np.random.default_rng(np.random.SeedSequence([seed, 0x51CE, s]))
-    h = np.searchsorted(pop.weight_cdf, rng.random(n_packets), side="right")
-    np.minimum(h, pop.n_hosts - 1, out=h)
+    # per-host packet counts ~ Multinomial(n_packets, weight), in random order
+    h = np.repeat(np.arange(pop.n_hosts), rng.multinomial(n_packets, pop.weight))
+    rng.shuffle(h)
     j = (rng.random(n_packets) * pop.card[h]).astype(np.int64)
     out = np.empty((n_packets, 2), dtype=np.uint32)
     out[:, 0] = pop.aips[h]

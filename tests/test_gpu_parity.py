@@ -1,0 +1,347 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Bar: the packed AT pool, clock, census, live counts and per-host histograms
+are bit-exact; FP32 estimates agree with the oracle's FP64 values within
+1e-6 relative, plus an absolute floor of g * 64 * 2^-52 that covers the
+oracle's own cancellation error in g ln Z_p - g ln Z_v (each logarithm is at
+most 32 ln 2 in magnitude, so its double rounding error is below 2^-47).
+"""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle.vate_ref import OracleSketch  # noqa: E402
+from paper_1812_00282_amd import _lib, streams  # noqa: E402
+from paper_1812_00282_amd.sketch import Config, Sketch  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+REL_TOL = 1e-6
+
+
+def _tol(ref_est, g):
+    return REL_TOL * np.abs(ref_est) + g * 64 * 2.0**-52
+
+
+def _pair(cfg, partition=None):
+    p = cfg.partition if partition is None else partition
+    gpu = Sketch(cfg, device="cuda")
+    ref = OracleSketch(cfg.log2_pool, cfg.width, cfg.k, cfg.g, cfg.seed_a, cfg.seed_b, p)
+    return gpu, ref
+
+
+def _u32(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+def _check_state(gpu, ref, what=""):
+    pool, t, bact0, closed = gpu.read_state()
+    assert (t, bact0, closed) == (ref.t, ref.bact0, ref.closed), what
+    exp = ref.packed_pool()
+    if not np.array_equal(pool, exp):
+        bad = np.flatnonzero(pool != exp)
+        raise AssertionError(f"{what}: {bad.size} pool bytes differ, first at {bad[:8]}: "
+                             f"gpu {pool[bad[:8]]} oracle {exp[bad[:8]]}")
+
+
+def _check_estimates(gpu, ref, hosts, kprime=None, hist=False, what=""):
+    est, live, hh = gpu.estimate(hosts, kprime=kprime, want_hist=hist)
+    torch.cuda.synchronize()
+    r_est, r_live, r_hist = ref.estimate(hosts, kprime=kprime, want_hist=hist)
+    assert np.array_equal(_u32(live), r_live), what
+    e = est.cpu().numpy().astype(np.float64)
+    err = np.abs(e - r_est)
+    ok = err <= _tol(r_est, ref.g)
+    assert ok.all(), f"{what}: {np.count_nonzero(~ok)} estimates off, worst rel " \
+                     f"{float(np.max(err / np.maximum(np.abs(r_est), 1e-300)))}"
+    if hist:
+        assert np.array_equal(_u32(hh), r_hist), what
+    return e, r_est
+
+
+# ------------------------------------------------------------------ small --
+
+def test_small_workload_every_slice():
+    """2^16 x 8-bit, g=128, k=4, 8 slices of 25k packets, 1000 hosts: pool,
+    clock and census bit-exact after every slice; every host's estimate,
+    live count and histogram checked at every slice for every k'."""
+    wl = streams.SMALL
+    pop = wl.population()
+    cfg = Config(wl.log2_pool, wl.width, wl.k, wl.g, seed_a=11, seed_b=12)
+    gpu, ref = _pair(cfg)
+    _check_state(gpu, ref, "after create")
+    for t in range(wl.n_slices):
+        pairs = wl.slice(pop, t)
+        gpu.ingest(pairs[:10001])          # ragged batches within the slice
+        gpu.ingest(pairs[10001:])
+        ref.ingest(pairs)
+        gpu.close_slice()
+        ref.close_slice()
+        _check_state(gpu, ref, f"slice {t}")
+        assert np.array_equal(gpu.census(), ref.census())
+        for kp in range(1, wl.k + 1):
+            _check_estimates(gpu, ref, pop.aips, kprime=kp, hist=(kp == wl.k),
+                             what=f"slice {t} k'={kp}")
+
+
+@pytest.mark.parametrize("partition", [0, 1])
+@pytest.mark.parametrize("w,k,c", [(4, 2, 12), (4, 7, 10), (8, 9, 13), (8, 100, 14),
+                                   (16, 129, 16), (16, 256, 17), (16, 1000, 16)])
+def test_widths_and_windows(w, k, c, partition):
+    """Every container width, windows across the LDS-histogram tiers
+    (k <= 64, <= 128, <= 256) and beyond (k = 1000, no histogram), both
+    partitions, for 2k+5 slices so that every block's ACT wraps."""
+    rng = np.random.default_rng(w * 100 + k + partition)
+    cfg = Config(c, w, k, 64, partition=partition, seed_a=k, seed_b=w)
+    gpu, ref = _pair(cfg)
+    hosts = rng.integers(0, 2**32, size=300, dtype=np.uint64).astype(np.uint32)
+    n_slices = 2 * k + 5 if k < 200 else k + 40
+    check_every = max(1, n_slices // 12)
+    for t in range(n_slices):
+        if t % 7 != 6:   # some empty slices
+            n = int(rng.integers(1, 3000))
+            pairs = np.stack([hosts[rng.integers(0, hosts.size, size=n)],
+                              rng.integers(0, 2**32, size=n, dtype=np.uint64).astype(np.uint32)], 1)
+            gpu.ingest(pairs)
+            ref.ingest(pairs)
+        gpu.close_slice()
+        ref.close_slice()
+        if t % check_every == 0 or t == n_slices - 1:
+            _check_state(gpu, ref, f"slice {t}")
+            kps = sorted({1, max(1, k // 3), k})
+            for kp in kps:
+                _check_estimates(gpu, ref, hosts, kprime=kp, hist=(k <= 256 and kp == k),
+                                 what=f"slice {t} k'={kp}")
+
+
+def test_small_pool_per_element_blocks():
+    """Pools whose blocks are shorter than a 16-byte chunk (the census and
+    preservation take the per-AT block path) and 4-bit ATs packed 8 per word
+    under heavy write contention."""
+    for c, w, k in [(5, 4, 2), (5, 4, 7), (4, 8, 3), (3, 16, 4), (6, 4, 5)]:
+        cfg = Config(c, w, k, 16, seed_a=c, seed_b=k)
+        gpu, ref = _pair(cfg)
+        rng = np.random.default_rng(c * 10 + k)
+        hosts = rng.integers(0, 2**32, size=20, dtype=np.uint64).astype(np.uint32)
+        for t in range(3 * k + 4):
+            n = int(rng.integers(0, 5000))
+            pairs = np.stack([hosts[rng.integers(0, hosts.size, size=n)],
+                              rng.integers(0, 2**32, size=n, dtype=np.uint64).astype(np.uint32)], 1)
+            gpu.ingest(pairs)
+            ref.ingest(pairs)
+            gpu.close_slice()
+            ref.close_slice()
+            _check_state(gpu, ref, f"c={c} w={w} k={k} slice {t}")
+            _check_estimates(gpu, ref, hosts, hist=True, what=f"c={c} w={w} k={k} slice {t}")
+
+
+def test_ragged_inputs_and_alignment():
+    """Packet counts that are not multiples of the 4-packet thread tile or the
+    1024-packet block, an 8-byte (not 16-byte) aligned pair pointer, empty
+    batches, and host counts around the 64-host wavefront and 256-host block."""
+    cfg = Config(14, 8, 5, 32, seed_a=3, seed_b=4)
+    gpu, ref = _pair(cfg)
+    rng = np.random.default_rng(5)
+    hosts = rng.integers(0, 2**32, size=600, dtype=np.uint64).astype(np.uint32)
+    n_total = 9999
+    pairs = np.stack([hosts[rng.integers(0, 600, size=n_total)],
+                      rng.integers(0, 2**32, size=n_total, dtype=np.uint64).astype(np.uint32)], 1)
+    dev = torch.from_numpy(pairs.view(np.int32)).cuda()
+    gpu.ingest(dev[1:1 + 1023])          # 8-byte aligned view
+    gpu.ingest(dev[1024:1027])
+    gpu.ingest(dev[1027:1027])           # empty
+    gpu.ingest(dev[1027:])
+    gpu.ingest(dev[:1])
+    ref.ingest(pairs)
+    gpu.close_slice()
+    ref.close_slice()
+    _check_state(gpu, ref, "ragged")
+    for n in (0, 1, 63, 64, 65, 255, 256, 257, 599):
+        if n == 0:
+            est, _, _ = gpu.estimate(hosts[:0])
+            assert est.numel() == 0
+            continue
+        _check_estimates(gpu, ref, hosts[:n], hist=True, what=f"{n} hosts")
+
+
+def test_call_order_errors():
+    cfg = Config(12, 8, 4, 32)
+    gpu = Sketch(cfg)
+    hosts = np.arange(10, dtype=np.uint32)
+    with pytest.raises(_lib.VateError) as e:
+        gpu.estimate(hosts)
+    assert e.value.code == _lib.VATE_E_STATE
+    gpu.close_slice()
+    with pytest.raises(_lib.VateError) as e:
+        gpu.estimate(hosts, kprime=0)
+    assert e.value.code == _lib.VATE_E_INVAL
+    with pytest.raises(_lib.VateError) as e:
+        gpu.estimate(hosts, kprime=5)
+    assert e.value.code == _lib.VATE_E_INVAL
+    est, live, _ = gpu.estimate(hosts)
+    torch.cuda.synchronize()
+    assert np.all(_u32(live) == 0) and np.all(est.cpu().numpy() == 0.0)
+    big = Sketch(Config(12, 16, 300, 32))
+    big.close_slice()
+    with pytest.raises(_lib.VateError) as e:
+        big.estimate(hosts, want_hist=True)
+    assert e.value.code == _lib.VATE_E_UNSUPPORTED
+
+
+def test_order_duplicates_and_padding_give_identical_pool():
+    """Sec. 4.2: SetATs of one AT in a slice all write the same value, so the
+    pool does not depend on packet order, duplicates, or padding the last
+    buffer with its last pair (checked for 8- and 4-bit ATs)."""
+    for w, k in [(8, 6), (4, 3)]:
+        rng = np.random.default_rng(w)
+        cfg = Config(10, w, k, 64, seed_a=1, seed_b=2)
+        a, b = Sketch(cfg), Sketch(cfg)
+        hosts = rng.integers(0, 2**32, size=30, dtype=np.uint64).astype(np.uint32)
+        for t in range(10):
+            n = 4000
+            pairs = np.stack([hosts[rng.integers(0, 30, size=n)],
+                              rng.integers(0, 2**32, size=n, dtype=np.uint64).astype(np.uint32)], 1)
+            a.ingest(pairs)
+            sh = pairs[rng.permutation(n)]
+            padded = np.concatenate([sh, sh[:1000], np.repeat(sh[-1:], 2**10 - 1000 % 2**10, 0)])
+            b.ingest(padded)
+            a.close_slice()
+            b.close_slice()
+            pa, *_ = a.read_state()
+            pb, *_ = b.read_state()
+            assert np.array_equal(pa, pb)
+
+
+def test_checkpoint_resume_is_bit_identical():
+    """8 slices straight == 4 slices, read_state, load into a fresh sketch,
+    4 more slices (state = ATP, t, BACT^0; Alg. 4)."""
+    wl = streams.SMALL
+    pop = wl.population()
+    cfg = Config(wl.log2_pool, wl.width, wl.k, wl.g, seed_a=21, seed_b=22)
+    a, b = Sketch(cfg), Sketch(cfg)
+    slices = [wl.slice(pop, t) for t in range(8)]
+    for t in range(8):
+        a.ingest(slices[t])
+        a.close_slice()
+    for t in range(4):
+        b.ingest(slices[t])
+        b.close_slice()
+    pool, t, bact0, closed = b.read_state()
+    c = Sketch(cfg)
+    c.load_state(pool, t, bact0, closed)
+    for t in range(4, 8):
+        c.ingest(slices[t])
+        c.close_slice()
+    pa = a.read_state()
+    pc = c.read_state()
+    assert np.array_equal(pa[0], pc[0]) and pa[1:] == pc[1:]
+    ea, la, _ = a.estimate(pop.aips)
+    ec, lc, _ = c.estimate(pop.aips)
+    assert torch.equal(ea, ec) and torch.equal(la, lc)
+    assert np.array_equal(a.census(), c.census())
+
+
+def test_estimate_precision_near_cancellation():
+    """Drive (u_v, u_p) to chosen values through load_state and compare the
+    FP32 estimate with the oracle's FP64, including Z_v == Z_p (exactly 0),
+    tiny differences, saturation (u_v = 0) and Z_v far above Z_p."""
+    c, w, k, g = 16, 8, 4, 1024
+    cfg = Config(c, w, k, g, seed_a=9, seed_b=10)
+    N = 1 << c
+    aip = 0x0A0B0C0D
+    ref = OracleSketch(c, w, k, g, 9, 10)
+    pids = np.array([ref.H(aip, i) for i in range(g)], dtype=np.int64)
+    uniq = np.unique(pids)
+    others = np.setdiff1d(np.arange(N), uniq)
+    rng = np.random.default_rng(0)
+    gpu = Sketch(cfg)
+    mult = np.bincount(np.searchsorted(uniq, pids), minlength=uniq.size)   # VATs per slot
+    cases = []
+    for host_active in (0, 1, 2, len(uniq) // 2, len(uniq) - 1, len(uniq)):
+        for frac in (0.0, 0.001, 0.3, 0.9, 0.999):
+            cases.append((host_active, int(frac * others.size)))
+    # Z_v == Z_p exactly (D = 0) and |D| = 1..3: u_p * g = N * u_v + D
+    for host_active in (100, 300, 500):
+        u_v = g - int(mult[:host_active].sum())
+        for D in (0, g, -g, 3 * g):
+            u_p = (N * u_v + D) // g
+            other_active = (uniq.size - host_active) + others.size - u_p
+            if 0 <= other_active <= others.size:
+                cases.append((-host_active, other_active))
+    for host_active, other_active in cases:
+        if host_active < 0:
+            chosen = uniq[:-host_active]
+        else:
+            chosen = rng.choice(uniq, host_active, replace=False)
+        act_pids = np.concatenate([chosen, rng.choice(others, other_active, replace=False)])
+        # an AT set in slice 0 holds its block's ACT, which is the block index at t = 0
+        vals = np.full(N, 2 * k, dtype=np.uint16)
+        vals[act_pids] = np.array([ref.block_of(int(p)) for p in act_pids], dtype=np.uint16)
+        ref.set_values(vals, 0, 0, True)
+        gpu.load_state(ref.packed_pool(), 0, 0, True)
+        _check_estimates(gpu, ref, np.array([aip], dtype=np.uint32),
+                         what=f"host_active={host_active} other={other_active}")
+
+
+# --------------------------------------------------------------- sweeps --
+
+@pytest.mark.parametrize("k,w,c", streams.SWEEP)
+def test_window_width_sweep(k, w, c):
+    """Window/width sweep on the small stream for 3k+8 slices (every block's
+    ACT wraps): pool bit-exact at checkpoints through the run, estimates and
+    live counts of all 1000 hosts (k' = k and k' = k/2) at the last slice."""
+    wl = streams.sweep_workload(k, w, c)
+    pop = wl.population()
+    cfg = Config(c, w, k, wl.g, seed_a=k, seed_b=c)
+    gpu, ref = _pair(cfg)
+    n_slices = wl.n_slices
+    checkpoints = {n_slices // 3, (2 * n_slices) // 3, n_slices - 1}
+    for t in range(n_slices):
+        pairs = wl.slice(pop, t)
+        gpu.ingest(pairs)
+        ref.ingest(pairs)
+        gpu.close_slice()
+        ref.close_slice()
+        if t in checkpoints:
+            _check_state(gpu, ref, f"k={k} slice {t}")
+    for kp in sorted({k, max(1, k // 2)}):
+        _check_estimates(gpu, ref, pop.aips, kprime=kp, hist=(kp == k and k <= 256),
+                         what=f"k={k} k'={kp}")
+
+
+# ------------------------------------------------------------ full size --
+
+def test_link40g_full_size_sampled():
+    """The 40 Gb/s-shaped workload at full size (2^28 x 8-bit pool, g=1024,
+    k=60, 1M hosts, 5M packets per slice) for 6 slices, in the launch
+    configuration the benchmark times: full pool bit-exact and census exact
+    after slices 0, 2 and 5; estimates of a 1% host sample against the oracle;
+    for all 1M hosts, the FP32 estimate against an FP64 evaluation of Eq. 11
+    from the GPU's own integer counts."""
+    wl = streams.LINK40G
+    pop = wl.population()
+    cfg = Config(wl.log2_pool, wl.width, wl.k, wl.g, seed_a=0xA5A5, seed_b=0x5A5A)
+    gpu, ref = _pair(cfg)
+    for t in range(6):
+        pairs = wl.slice(pop, t)
+        dev = torch.from_numpy(pairs.view(np.int32)).cuda()
+        gpu.ingest(dev)
+        ref.ingest(pairs)
+        gpu.close_slice()
+        ref.close_slice()
+        if t in (0, 2, 5):
+            _check_state(gpu, ref, f"slice {t}")
+            assert np.array_equal(gpu.census(), ref.census()), t
+    sample = pop.aips[np.random.default_rng(0).choice(pop.n_hosts, 10_000, replace=False)]
+    _check_estimates(gpu, ref, sample, what="1% sample")
+    est, live, _ = gpu.estimate(pop.aips)
+    cen = gpu.census()
+    torch.cuda.synchronize()
+    u_p = max(int(cen[wl.k]), 1)
+    u_v = np.maximum(wl.g - _u32(live).astype(np.int64), 1)
+    f64 = wl.g * (math.log(u_p / 2**wl.log2_pool)) - wl.g * np.log(u_v / wl.g)
+    e = est.cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(e - f64) <= _tol(f64, wl.g))
