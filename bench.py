@@ -79,6 +79,9 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=60)
     ap.add_argument("--warmup", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one 1 GiB device-to-device copy (reference kernel for "
+                         "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE readings)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"),
                     help="HBM traffic per estimate launch measured with rocprofv3 counters")
     args = ap.parse_args()
@@ -119,6 +122,14 @@ def main() -> int:
         if ev is not None:
             ev[3].record()
 
+    if args.copy_calibration:
+        src = torch.ones(1 << 30, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("[bench] calibration copy of 1 GiB done")
+        del src, dst
     log(f"[bench] warmup {args.warmup}")
     for s in range(args.warmup):
         step(s)
