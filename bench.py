@@ -31,6 +31,26 @@ def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
 
+def measured_traffic(path=None):
+    """HBM bytes per estimate launch (FETCH_SIZE + WRITE_SIZE, calibrated) from
+    a committed rocprofv3 summary, or None if the kernel source has changed
+    since the counters were taken."""
+    import glob
+    import hashlib
+
+    src = os.path.join(ROOT, "paper_1812_00282_amd", "csrc", "vate.hip")
+    cur = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    paths = [path] if path else sorted(glob.glob(os.path.join(ROOT, "profiles", "*.txt")),
+                                       key=os.path.getmtime, reverse=True)
+    for p in paths:
+        for line in open(p):
+            if line.startswith("TRAFFIC k_estimate"):
+                fields = dict(f.split("=", 1) for f in line.split()[2:])
+                if fields.get("csrc_vate_hip_sha256_16") == cur:
+                    return float(fields["bytes_per_launch"]), os.path.relpath(p, ROOT)
+    return None, None
+
+
 def cpu_baseline(wl, pop, slices, budget_hosts: int = 20_000) -> dict:
     """The CPU oracle, single-threaded, on a bounded sample of the same
     workload: one slice of ingest (5M packets), the pool scan behind Z_p,
@@ -82,8 +102,9 @@ def main() -> int:
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device-to-device copy (reference kernel for "
                          "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE readings)")
-    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"),
-                    help="HBM traffic per estimate launch measured with rocprofv3 counters")
+    ap.add_argument("--profile-summary", default=None,
+                    help="rocprofv3 summary holding the dominant kernel's HBM traffic "
+                         "(default: the newest profiles/*.txt with a TRAFFIC line)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the VATE "
@@ -150,13 +171,10 @@ def main() -> int:
     # dominant kernel: the per-host estimate gather
     bytes_per_host = 4 + wl.g * wl.width // 8 + 4
     achieved = bytes_per_host * pop.n_hosts / (est_ms * 1e-3) / 1e9
-    traffic = None
-    if os.path.exists(args.traffic_json):
-        with open(args.traffic_json) as f:
-            tj = json.load(f)
-        traffic = tj.get("estimate_bytes_per_launch")
+    traffic, traffic_src = measured_traffic(args.profile_summary)
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                "traffic_source": traffic_src,
                 "kernel": "k_estimate<8,false>",
                 "algorithmic_bytes_per_launch": bytes_per_host * pop.n_hosts,
                 "avg_launch_ms": est_ms,

@@ -43,10 +43,19 @@ __host__ __device__ __forceinline__ const unsigned long long *census_of(const De
 }
 constexpr int kMaxHistK = 256;      // per-host histogram limit (LDS budget)
 
-static size_t state_bytes_for(uint32_t k)
+// State block layout: header, k census counters, then (256-byte aligned) the
+// activity bitmap of N bits.
+static size_t bitmap_offset(uint32_t k)
 {
     size_t b = kStateHeader + 8ull * k;
     return (b + 255) & ~size_t(255);
+}
+
+static size_t state_bytes_for(uint32_t k, uint64_t N)
+{
+    size_t bm = (size_t)((N + 7) / 8);
+    if (bm < 16) bm = 16;
+    return (bitmap_offset(k) + bm + 255) & ~size_t(255);
 }
 
 // ---------------------------------------------------------------------------
@@ -225,9 +234,25 @@ __global__ void __launch_bounds__(256) k_ingest(Geo G, const uint32_t *__restric
 // ---------------------------------------------------------------------------
 constexpr uint32_t kCensusLdsBins = 4096;
 
+// The same pass writes the activity bitmap: bit p is set iff AT p is active
+// for the longest window k at the end of this slice (value != 2k and
+// distance < k).  The bitmap (N bits; 32 MiB for 2^28 ATs) is small enough to
+// stay resident in the MI355X's 256 MB Infinity Cache, so the per-host gather
+// in k_estimate reads bits from it instead of AT bytes from HBM.
+template <int W>
+__device__ __forceinline__ void store_bits(uint8_t *__restrict__ bitmap, uint64_t ch, uint32_t bits)
+{
+    if constexpr (W == 8)
+        reinterpret_cast<uint16_t *>(bitmap)[ch] = (uint16_t)bits;   // 16 ATs per chunk
+    else if constexpr (W == 4)
+        reinterpret_cast<uint32_t *>(bitmap)[ch] = bits;             // 32 ATs per chunk
+    else
+        bitmap[ch] = (uint8_t)bits;                                  // 8 ATs per chunk
+}
+
 template <int W>
 __global__ void __launch_bounds__(256) k_census(Geo G, const uint4 *__restrict__ pool4, uint64_t nchunks,
-                                                DevState *__restrict__ st)
+                                                DevState *__restrict__ st, uint8_t *__restrict__ bitmap)
 {
     __shared__ uint32_t hist[kCensusLdsBins];
     const bool lds = G.k <= kCensusLdsBins;
@@ -248,29 +273,35 @@ __global__ void __launch_bounds__(256) k_census(Geo G, const uint4 *__restrict__
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            if (v[u].x == pat && v[u].y == pat && v[u].z == pat && v[u].w == pat) continue;
-            const uint64_t p0 = (c0 + u * stride) * E;
-            uint32_t bid0 = 0, act0 = 0;
-            uint64_t next = 0;
-            if (G.fast_blocks) {
-                bid0 = block_of(G, (uint32_t)p0);
-                act0 = block_act(G, bact0, bid0);
-                next = block_start(G, bid0 + 1);
-            }
-            for (uint32_t e = 0; e < E; ++e) {
-                uint32_t val = chunk_get<W>(v[u], e);
-                if (val == G.twok) continue;
-                uint32_t act;
-                if (G.fast_blocks)
-                    act = p0 + e < next ? act0 : block_act(G, bact0, bid0 + 1);
-                else
-                    act = block_act(G, bact0, block_of(G, (uint32_t)(p0 + e)));
-                uint32_t d = at_dist(G, act, val);
-                if (d < G.k) {
-                    if (lds) atomicAdd(&hist[d], 1u);
-                    else atomicAdd(&census_of(st)[d], 1ull);
+            const uint64_t ch = c0 + u * stride;
+            if (ch >= nchunks) continue;
+            uint32_t bits = 0;
+            if (!(v[u].x == pat && v[u].y == pat && v[u].z == pat && v[u].w == pat)) {
+                const uint64_t p0 = ch * E;
+                uint32_t bid0 = 0, act0 = 0;
+                uint64_t next = 0;
+                if (G.fast_blocks) {
+                    bid0 = block_of(G, (uint32_t)p0);
+                    act0 = block_act(G, bact0, bid0);
+                    next = block_start(G, bid0 + 1);
+                }
+                for (uint32_t e = 0; e < E; ++e) {
+                    uint32_t val = chunk_get<W>(v[u], e);
+                    if (val == G.twok) continue;
+                    uint32_t act;
+                    if (G.fast_blocks)
+                        act = p0 + e < next ? act0 : block_act(G, bact0, bid0 + 1);
+                    else
+                        act = block_act(G, bact0, block_of(G, (uint32_t)(p0 + e)));
+                    uint32_t d = at_dist(G, act, val);
+                    if (d < G.k) {
+                        bits |= 1u << e;
+                        if (lds) atomicAdd(&hist[d], 1u);
+                        else atomicAdd(&census_of(st)[d], 1ull);
+                    }
                 }
             }
+            store_bits<W>(bitmap, ch, bits);
         }
     }
     __syncthreads();
@@ -317,6 +348,7 @@ constexpr int kEstU = 16;   // VAT gathers in flight per thread
 template <int W, bool HIST>
 __global__ void __launch_bounds__(256) k_estimate(Geo G, const uint8_t *__restrict__ pool,
                                                   const DevState *__restrict__ st,
+                                                  const uint8_t *__restrict__ bitmap,
                                                   const uint32_t *__restrict__ hosts, uint32_t n,
                                                   uint32_t kprime, float *__restrict__ est,
                                                   uint32_t *__restrict__ live_out,
@@ -331,24 +363,33 @@ __global__ void __launch_bounds__(256) k_estimate(Geo G, const uint8_t *__restri
     }
     const uint64_t active_pool = pool_active(st, kprime);
     const uint32_t bact0 = st->bact0;
+    // The bitmap answers CheckAT(., k) directly; the AT value (for its
+    // distance) is only fetched for VATs that are active at all, and only
+    // when a shorter window or the histogram needs it.
+    const bool need_dist = HIST || kprime < G.k;
     const uint32_t h = blockIdx.x * blockDim.x + threadIdx.x;
     const bool valid = h < n;
     const uint32_t key = host_key(G, valid ? hosts[h] : 0u);
     uint32_t live = 0, live_k = 0;
     for (uint32_t i0 = 0; i0 < G.g; i0 += kEstU) {
-        uint32_t pid[kEstU], val[kEstU];
+        uint32_t pid[kEstU], byte[kEstU];
 #pragma unroll
         for (int u = 0; u < kEstU; ++u) pid[u] = vat_pid(G, key, i0 + u);
 #pragma unroll
         for (int u = 0; u < kEstU; ++u)
-            val[u] = (valid && i0 + u < G.g) ? load_at<W>(pool, pid[u]) : G.twok;
+            byte[u] = (valid && i0 + u < G.g) ? bitmap[pid[u] >> 3] : 0u;
 #pragma unroll
         for (int u = 0; u < kEstU; ++u) {
-            if (val[u] == G.twok) continue;
+            if (!((byte[u] >> (pid[u] & 7u)) & 1u)) continue;
+            if (!need_dist) {
+                ++live;
+                continue;
+            }
+            const uint32_t val = load_at<W>(pool, pid[u]);
             const uint32_t act = block_act(G, bact0, block_of(G, pid[u]));
-            const uint32_t d = at_dist(G, act, val[u]);
+            const uint32_t d = at_dist(G, act, val);
             live += d < kprime;
-            if (HIST && d < G.k) {
+            if (HIST) {
                 ++live_k;
                 atomicAdd(&my[(d >> 1) * 65 + lane], 1u << ((d & 1u) << 4));
             }
@@ -457,6 +498,7 @@ struct vate_sketch {
     Geo G;
     uint8_t *pool;
     DevState *st;
+    uint8_t *bitmap;             // activity bitmap inside the state block
     size_t pool_bytes, state_bytes;
     uint64_t max_block_chunks;   // chunks a due block can overlap
     int closed;                  // 1: slice ended, estimates allowed
@@ -502,8 +544,8 @@ template <int W>
 static void launch_census(vate_sketch *s, hipStream_t st)
 {
     uint64_t nch = s->pool_bytes / 16;
-    k_census<W><<<grid_for(nch, 256 * 4, 4096), 256, 0, st>>>(s->G, reinterpret_cast<const uint4 *>(s->pool),
-                                                               nch, s->st);
+    k_census<W><<<grid_for(nch, 256 * 4, 2048), 256, 0, st>>>(s->G, reinterpret_cast<const uint4 *>(s->pool),
+                                                               nch, s->st, s->bitmap);
 }
 
 template <int W>
@@ -556,11 +598,12 @@ static void launch_estimate(vate_sketch *s, const uint32_t *hosts, uint32_t n, u
         const uint32_t k = s->G.k;
         const unsigned threads = k <= 64 ? 256 : k <= 128 ? 128 : 64;
         const size_t lds = (size_t)(threads / 64) * ((k + 1) / 2 + 1) * 65 * sizeof(uint32_t);
-        k_estimate<W, true><<<grid_for(n, threads, 1u << 30), threads, lds, st>>>(s->G, s->pool, s->st, hosts, n,
-                                                                                  kprime, est, live, hist);
+        k_estimate<W, true><<<grid_for(n, threads, 1u << 30), threads, lds, st>>>(s->G, s->pool, s->st, s->bitmap,
+                                                                                  hosts, n, kprime, est, live,
+                                                                                  hist);
     } else {
-        k_estimate<W, false><<<grid_for(n, 256, 1u << 30), 256, 0, st>>>(s->G, s->pool, s->st, hosts, n, kprime,
-                                                                         est, live, nullptr);
+        k_estimate<W, false><<<grid_for(n, 256, 1u << 30), 256, 0, st>>>(s->G, s->pool, s->st, s->bitmap,
+                                                                         hosts, n, kprime, est, live, nullptr);
     }
 }
 
@@ -573,7 +616,7 @@ int vate_state_bytes(const vate_params *p, size_t *pool_bytes, size_t *state_byt
     int rc = make_geo(p, &G, &why);
     if (rc != VATE_OK) return rc;
     if (pool_bytes) *pool_bytes = (size_t)(G.N * p->width / 8);
-    if (state_bytes) *state_bytes = state_bytes_for(p->k);
+    if (state_bytes) *state_bytes = state_bytes_for(p->k, G.N);
     return VATE_OK;
 }
 
@@ -595,7 +638,8 @@ int vate_create(const vate_params *p, void *pool_dev, void *state_dev, void *str
     s->pool = static_cast<uint8_t *>(pool_dev);
     s->st = static_cast<DevState *>(state_dev);
     s->pool_bytes = (size_t)(G.N * p->width / 8);
-    s->state_bytes = state_bytes_for(p->k);
+    s->state_bytes = state_bytes_for(p->k, G.N);
+    s->bitmap = static_cast<uint8_t *>(state_dev) + bitmap_offset(p->k);
     uint64_t maxb = 0;
     for (uint32_t i = 0; i < G.twok; ++i)
         maxb = std::max<uint64_t>(maxb, block_start(G, i + 1) - block_start(G, i));
