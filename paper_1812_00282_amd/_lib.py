@@ -60,7 +60,22 @@ _SIGS = {
     "vate_destroy": (None, [_vp]),
     "vate_host_hash": (_u32, [ctypes.POINTER(VateParams), _u32, _u32, _u32]),
     "vate_host_block": (_u32, [ctypes.POINTER(VateParams), _u64]),
+    # learned estimator (include/vate_mlp.h)
+    "vate_mlp_pack": (_i32, [_vp, _vp, _vp]),
+    "vate_mlp_forward": (_i32, [_vp, _vp, _vp, _sz, _vp, _vp]),
+    "vate_mlp_train_step": (_i32, [_vp, _vp, _vp, _vp, _sz, _vp, _vp, _vp]),
+    "vate_mlp_adam": (_i32, [_vp, _vp, _vp, _vp, _u32, ctypes.c_float, ctypes.c_float,
+                             ctypes.c_float, ctypes.c_float, _vp]),
+    "vate_mlp_fill": (_i32, [_vp, _sz, ctypes.c_float, _vp]),
+    "vate_mlp_features": (_i32, [_vp, _vp, _sz, _u32, _u32, ctypes.c_float, _vp, _vp, _vp]),
+    "vate_estimate_learned": (_i32, [_vp, _vp, _sz, _vp, _vp, _vp, _vp]),
+    "vate_mlp_mfma_selftest": (_i32, [_vp, _vp, _vp, _vp]),
 }
+
+MLP_FEATURES = 64
+MLP_HIDDEN = 64
+MLP_PARAMS = 8385
+MLP_WEIGHT_BYTES = 25600
 
 _lib = None
 

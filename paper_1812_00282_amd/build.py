@@ -15,7 +15,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libvate.so")
 
-SOURCES = ["vate.hip"]
+SOURCES = ["vate.hip", "mlp.hip"]
 ARCH = "gfx950"
 
 

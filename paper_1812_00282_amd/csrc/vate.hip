@@ -17,6 +17,8 @@
 
 #include "vate.h"
 #include "vate_core.h"
+#include "vate_mlp.h"
+#include "mlp_core.h"
 
 namespace vate {
 
@@ -420,6 +422,96 @@ __global__ void __launch_bounds__(256) k_estimate(Geo G, const uint8_t *__restri
 }
 
 // ---------------------------------------------------------------------------
+// k_estimate_learned: the gather of k_estimate (histogram path, window k)
+// followed, in the same workgroup, by the learned estimator on the matrix
+// cores.  Each wavefront's 64 hosts are fed to the network as four 16-row
+// tiles built straight from the LDS histograms; the closed form is kept as
+// the output where the network's result is not finite.
+// ---------------------------------------------------------------------------
+constexpr int kLearnMaxK = VATE_MLP_FEATURES - 2;
+
+template <int W>
+__global__ void __launch_bounds__(256) k_estimate_learned(Geo G, const uint8_t *__restrict__ pool,
+                                                          const DevState *__restrict__ st,
+                                                          const uint8_t *__restrict__ bitmap,
+                                                          const uint32_t *__restrict__ hosts, uint32_t n,
+                                                          const mlp::Packed *__restrict__ P,
+                                                          float *__restrict__ est_out,
+                                                          float *__restrict__ cf_out)
+{
+    constexpr int ROWS = (kLearnMaxK + 1) / 2 + 1;   // packed 16-bit bin pairs + live row
+    __shared__ uint32_t hist_all[4][ROWS * 65];
+    __shared__ __attribute__((aligned(16))) uint16_t xs_all[4][16 * mlp::LDS_STRIDE];
+    __shared__ __attribute__((aligned(16))) uint16_t a1_all[4][16 * mlp::LDS_STRIDE];
+    __shared__ float cf_all[4][64];
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+    const uint32_t rows = (G.k + 1) / 2;
+    uint32_t *my = hist_all[wave];
+    for (uint32_t r = 0; r < rows; ++r) my[r * 65 + lane] = 0;
+    const uint64_t active_pool = pool_active(st, G.k);
+    const uint32_t bact0 = st->bact0;
+    const uint32_t h = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = h < n;
+    const uint32_t key = host_key(G, valid ? hosts[h] : 0u);
+    uint32_t live = 0;
+    for (uint32_t i0 = 0; i0 < G.g; i0 += kEstU) {
+        uint32_t pid[kEstU], byte[kEstU];
+#pragma unroll
+        for (int u = 0; u < kEstU; ++u) pid[u] = vat_pid(G, key, i0 + u);
+#pragma unroll
+        for (int u = 0; u < kEstU; ++u)
+            byte[u] = (valid && i0 + u < G.g) ? bitmap[pid[u] >> 3] : 0u;
+#pragma unroll
+        for (int u = 0; u < kEstU; ++u) {
+            if (!((byte[u] >> (pid[u] & 7u)) & 1u)) continue;
+            const uint32_t val = load_at<W>(pool, pid[u]);
+            const uint32_t d = at_dist(G, block_act(G, bact0, block_of(G, pid[u])), val);
+            ++live;
+            atomicAdd(&my[(d >> 1) * 65 + lane], 1u << ((d & 1u) << 4));
+        }
+    }
+    const float cf = estimate_from_counts(G.g - live, G.N - active_pool, G.g, G.c);
+    my[rows * 65 + lane] = live;
+    cf_all[wave][lane] = cf;
+    if (valid) cf_out[h] = cf;
+    const float occupancy = (float)active_pool / (float)G.N;
+    const float fg = (float)G.g;
+    const int q = lane >> 4, c = lane & 15;
+    uint16_t *xs = xs_all[wave];
+    __syncthreads();
+    for (int t = 0; t < 4; ++t) {
+        // features of hosts 16t .. 16t+15 of this wavefront (row m = host - 16t)
+        for (int e = lane; e < 16 * VATE_MLP_FEATURES; e += 64) {
+            const int m = e >> 6, f = e & 63, host = 16 * t + m;
+            float x = 0.f;
+            if (f < (int)G.k)
+                x = (float)((my[(f >> 1) * 65 + host] >> ((f & 1) << 4)) & 0xFFFFu) / fg;
+            else if (f == (int)G.k)
+                x = (float)my[rows * 65 + host] / fg;
+            else if (f == (int)G.k + 1)
+                x = occupancy;
+            xs[m * mlp::LDS_STRIDE + f] = mlp::bf16_bits(x);
+        }
+        __syncthreads();
+        float r4[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) r4[r] = logf(fmaxf(cf_all[wave][16 * t + 4 * q + r], 1.0f));
+        mlp::f32x4 z1[4], z2[4];
+        float a2v[4][4], o4[4];
+        mlp::forward16(P, xs, a1_all[wave], r4, z1, z2, a2v, o4);
+        if (c < 4) {
+            const int host = 16 * t + 4 * q + c;
+            const uint32_t hg = blockIdx.x * blockDim.x + wave * 64 + host;
+            if (hg < n) {
+                const float e = expf(o4[c]);
+                est_out[hg] = isfinite(e) ? e : cf_all[wave][host];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Slice advance: BACT^0 = (BACT^0 + 1) mod 2k, t = t + 1 (Alg. 4 end of loop),
 // census cleared for the new slice.
 // ---------------------------------------------------------------------------
@@ -607,6 +699,14 @@ static void launch_estimate(vate_sketch *s, const uint32_t *hosts, uint32_t n, u
     }
 }
 
+template <int W>
+static void launch_estimate_learned(vate_sketch *s, const uint32_t *hosts, uint32_t n, const void *weights,
+                                    float *est, float *cf, hipStream_t st)
+{
+    k_estimate_learned<W><<<grid_for(n, 256, 1u << 30), 256, 0, st>>>(
+        s->G, s->pool, s->st, s->bitmap, hosts, n, static_cast<const mlp::Packed *>(weights), est, cf);
+}
+
 extern "C" {
 
 int vate_state_bytes(const vate_params *p, size_t *pool_bytes, size_t *state_bytes)
@@ -713,6 +813,27 @@ int vate_estimate(vate_sketch *s, const uint32_t *hosts_dev, size_t n_hosts, uin
     else if (s->p.width == 8) launch_estimate<8>(s, hosts_dev, n, kprime, est_dev, live_dev, hist_dev, st);
     else launch_estimate<16>(s, hosts_dev, n, kprime, est_dev, live_dev, hist_dev, st);
     return check_launch(s, "estimate");
+}
+
+int vate_estimate_learned(vate_sketch *s, const uint32_t *hosts_dev, size_t n_hosts, const void *weights_dev,
+                          float *est_dev, float *est_cf_dev, void *stream)
+{
+    if (!s) return VATE_E_INVAL;
+    if (s->dead) return VATE_E_DEVICE;
+    if (!s->closed) return fail(s, VATE_E_STATE, "estimate needs a closed slice (call vate_close_slice)");
+    if (s->p.k > (uint32_t)kLearnMaxK) return fail(s, VATE_E_UNSUPPORTED, "learned estimator needs k + 2 <= 64");
+    if (n_hosts > 0xFFFFFFFFull - 1024) return fail(s, VATE_E_INVAL, "too many hosts");
+    if (n_hosts == 0) return VATE_OK;
+    if (!hosts_dev || !est_dev || !est_cf_dev || !weights_dev || (reinterpret_cast<uintptr_t>(hosts_dev) & 3u) ||
+        (reinterpret_cast<uintptr_t>(est_dev) & 3u) || (reinterpret_cast<uintptr_t>(est_cf_dev) & 3u) ||
+        (reinterpret_cast<uintptr_t>(weights_dev) & 255u))
+        return fail(s, VATE_E_INVAL, "hosts/est/est_cf must be 4-byte and weights 256-byte aligned, non-NULL");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const uint32_t n = (uint32_t)n_hosts;
+    if (s->p.width == 4) launch_estimate_learned<4>(s, hosts_dev, n, weights_dev, est_dev, est_cf_dev, st);
+    else if (s->p.width == 8) launch_estimate_learned<8>(s, hosts_dev, n, weights_dev, est_dev, est_cf_dev, st);
+    else launch_estimate_learned<16>(s, hosts_dev, n, weights_dev, est_dev, est_cf_dev, st);
+    return check_launch(s, "estimate_learned");
 }
 
 int vate_read_census(vate_sketch *s, uint64_t *census_host, void *stream)

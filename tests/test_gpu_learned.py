@@ -1,0 +1,171 @@
+"""Parity of the learned-estimator kernels (BF16 matrix cores, FP32
+accumulation) with the FP64 CPU oracle that mirrors their BF16 rounding
+points (oracle/mlp_ref.py).
+
+Bar: forward outputs and every gradient tensor within a relative L2 error of
+1e-3 (an occasional BF16 rounding of an activation may land on the other side
+of a rounding boundary in FP32 vs FP64, moving that activation by one BF16
+step, 2^-8 relative); the fragment-layout self-test and the features exact;
+Adam within 1e-6 relative.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import mlp_ref as M  # noqa: E402
+from oracle.vate_ref import OracleSketch  # noqa: E402
+from paper_1812_00282_amd import learned as L  # noqa: E402
+from paper_1812_00282_amd import streams  # noqa: E402
+from paper_1812_00282_amd.sketch import Config, Sketch  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def _bf16_bits(x: np.ndarray) -> np.ndarray:
+    return (M.bf16_round(x).astype(np.float32).view(np.uint32) >> 16).astype(np.uint16)
+
+
+def _rel_l2(a, b):
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+
+
+def _problem(seed, n):
+    rng = np.random.default_rng(seed)
+    p = M.init_params(seed, zero_out=False)
+    p.w3 = rng.standard_normal(64) * 0.3
+    p.b1 = rng.standard_normal(64) * 0.1
+    p.b2 = rng.standard_normal(64) * 0.1
+    p.b3 = 0.2
+    x = rng.random((n, 64)) * rng.choice([0.0, 1.0], size=(n, 64), p=[0.3, 0.7])
+    r = rng.standard_normal(n) * 2
+    y = r + rng.standard_normal(n) * 0.5
+    return p, x, r, y
+
+
+def _to_dev(p, x, r, y=None):
+    theta = torch.from_numpy(L.theta_from(p.flat() | {"b3": p.b3})).cuda()
+    w = L.pack(theta, L.new_weights())
+    xd = torch.from_numpy(_bf16_bits(x).view(np.int16)).cuda()
+    rd = torch.from_numpy(r.astype(np.float32)).cuda()
+    yd = torch.from_numpy(y.astype(np.float32)).cuda() if y is not None else None
+    return theta, w, xd, rd, yd
+
+
+def test_mfma_fragment_layout():
+    rng = np.random.default_rng(0)
+    A = M.bf16_round(rng.standard_normal((16, 32)))
+    B = M.bf16_round(rng.standard_normal((32, 16)))
+    d = L.mfma_selftest(torch.from_numpy(_bf16_bits(A).view(np.int16)).cuda(),
+                        torch.from_numpy(_bf16_bits(B).view(np.int16)).cuda())
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(d.cpu().numpy(), A @ B, rtol=1e-5, atol=1e-5)
+
+
+@pytest.mark.parametrize("n", [1, 16, 63, 64, 1000, 4097])
+def test_forward_parity(n):
+    p, x, r, _ = _problem(n, n)
+    _, w, xd, rd, _ = _to_dev(p, x, r)
+    o = L.forward(w, xd, rd)
+    torch.cuda.synchronize()
+    ref, _ = M.forward(p, x, r)
+    got = o.cpu().numpy()
+    assert _rel_l2(got, ref) < 1e-3
+    assert np.max(np.abs(got - ref)) < 2e-2
+
+
+@pytest.mark.parametrize("n", [64, 200, 4096])
+def test_gradient_parity(n):
+    p, x, r, y = _problem(100 + n, n)
+    _, w, xd, rd, yd = _to_dev(p, x, r, y)
+    grad = torch.zeros(L.MLP_PARAMS, dtype=torch.float32, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    L.train_step(w, xd, rd, yd, grad, loss)
+    torch.cuda.synchronize()
+    o, cache = M.forward(p, x, r)
+    ref_loss, do = M.loss_grad(o, y)
+    g = M.backward(p, cache, do)
+    got = L.params_from(grad)
+    assert loss.item() == pytest.approx(ref_loss, rel=1e-3)
+    for name in ("W1", "b1", "W2", "b2", "w3"):
+        assert _rel_l2(got[name], getattr(g, name)) < 1e-3, name
+    assert got["b3"] == pytest.approx(g.b3, rel=1e-3, abs=1e-6)
+
+
+def test_adam_parity():
+    rng = np.random.default_rng(9)
+    p = M.init_params(9, zero_out=False)
+    theta = torch.from_numpy(L.theta_from(p.flat() | {"b3": p.b3})).cuda()
+    m = torch.zeros_like(theta)
+    v = torch.zeros_like(theta)
+    st = M.adam_init(p)
+    for step in range(1, 4):
+        gnp = rng.standard_normal(L.MLP_PARAMS).astype(np.float32)
+        g = M.Params(**{k: (val if isinstance(val, float) else val)
+                        for k, val in L.params_from(gnp).items()})
+        L.adam(theta, torch.from_numpy(gnp).cuda(), m, v, step, lr=1e-2)
+        M.adam_step(p, g, st, lr=1e-2)
+    torch.cuda.synchronize()
+    got = L.params_from(theta)
+    for name in ("W1", "b1", "W2", "b2", "w3"):
+        np.testing.assert_allclose(got[name], getattr(p, name), rtol=1e-6, atol=1e-7)
+
+
+def _small_sketch():
+    wl = streams.SMALL
+    pop = wl.population()
+    cfg = Config(wl.log2_pool, wl.width, wl.k, wl.g, seed_a=31, seed_b=32)
+    gpu = Sketch(cfg)
+    ref = OracleSketch(wl.log2_pool, wl.width, wl.k, wl.g, 31, 32)
+    for t in range(wl.n_slices):
+        pairs = wl.slice(pop, t)
+        gpu.ingest(pairs)
+        ref.ingest(pairs)
+        gpu.close_slice()
+        ref.close_slice()
+    return wl, pop, gpu, ref
+
+
+def test_features_and_fused_learned_estimate():
+    """Features from the estimate's histogram match the oracle bit for bit;
+    the fused gather+network kernel equals estimate -> features -> forward on
+    the GPU exactly, and the oracle's network within tolerance."""
+    wl, pop, gpu, ref = _small_sketch()
+    hosts = pop.aips
+    est, live, hist = gpu.estimate(hosts, want_hist=True)
+    cen = gpu.census()
+    occ = (2**wl.log2_pool - int(cen[wl.k])) / 2**wl.log2_pool
+    x, r = L.features(hist, est, wl.k, wl.g, occ)
+    torch.cuda.synchronize()
+    r_est, r_live, r_hist = ref.estimate(hosts, want_hist=True)
+    xo = M.features(r_hist, r_hist[:, :wl.k].sum(1), wl.g, wl.k,
+                    (ref.N - ref.pool_inactive(wl.k)) / ref.N)
+    assert np.array_equal(x.cpu().numpy().view(np.uint16), _bf16_bits(xo))
+    np.testing.assert_allclose(r.cpu().numpy(), np.log(np.maximum(r_est, 1.0)), rtol=1e-6, atol=1e-6)
+
+    p, _, _, _ = _problem(5, 1)
+    p.w3 = np.random.default_rng(6).standard_normal(64) * 0.05
+    theta = torch.from_numpy(L.theta_from(p.flat() | {"b3": p.b3})).cuda()
+    w = L.pack(theta, L.new_weights())
+    o = L.forward(w, x, r)
+    e_learn, e_cf = L.estimate_learned(gpu, hosts, w)
+    torch.cuda.synchronize()
+    assert torch.equal(e_cf, est)
+    np.testing.assert_allclose(e_learn.cpu().numpy(), np.exp(o.cpu().numpy().astype(np.float64)), rtol=1e-6)
+    ref_o, _ = M.forward(p, xo, np.log(np.maximum(r_est, 1.0)))
+    assert _rel_l2(e_learn.cpu().numpy(), np.exp(ref_o)) < 1e-3
+
+
+def test_zero_output_layer_gives_closed_form():
+    """Before training (w3 = 0, b3 = 0) the learned estimate is the closed
+    form clamped below at 1."""
+    wl, pop, gpu, ref = _small_sketch()
+    p = M.init_params(3, zero_out=True)
+    theta = torch.from_numpy(L.theta_from(p.flat() | {"b3": 0.0})).cuda()
+    w = L.pack(theta, L.new_weights())
+    e_learn, e_cf = L.estimate_learned(gpu, pop.aips, w)
+    torch.cuda.synchronize()
+    cf = e_cf.cpu().numpy()
+    np.testing.assert_allclose(e_learn.cpu().numpy(), np.maximum(cf, 1.0), rtol=2e-6)
