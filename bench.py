@@ -2,9 +2,12 @@
 
 One step = one 1 s time slice of the 40 Gb/s-shaped workload, the whole hot
 path: advance + two-block preservation, ingest of 5M packets (SetAT), pool
-census, and estimation of all 1M ANet hosts over the k = 60 slice window.
-Inputs (the packet stream and host list) are resident in HBM before the
-timed region starts.  Prints one JSON line.
+census, and estimation of all 1M ANet hosts over the k = 60 slice window,
+both by the closed form (Eq. 11) and by the learned estimator (one pass over
+the VATs gives both).  Inputs (the packet stream and host list) are resident
+in HBM before the timed region starts.  After the timed region the learned
+and closed-form estimators are compared on held-out probe episodes with
+known cardinalities.  Prints one JSON line.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -31,22 +34,30 @@ def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
 
-def measured_traffic(path=None):
-    """HBM bytes per estimate launch (FETCH_SIZE + WRITE_SIZE, calibrated) from
-    a committed rocprofv3 summary, or None if the kernel source has changed
-    since the counters were taken."""
-    import glob
+def kernel_source_hash() -> str:
+    """Hash of the sources that define the estimate-phase kernels."""
     import hashlib
 
-    src = os.path.join(ROOT, "paper_1812_00282_amd", "csrc", "vate.hip")
-    cur = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in ("vate.hip", "vate_core.h", "mlp_core.h"):
+        h.update(open(os.path.join(ROOT, "paper_1812_00282_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(path=None):
+    """HBM bytes per slice of the estimate phase (FETCH_SIZE + WRITE_SIZE of
+    its kernels, calibrated) from a committed rocprofv3 summary, or None if the
+    kernel sources have changed since the counters were taken."""
+    import glob
+
+    cur = kernel_source_hash()
     paths = [path] if path else sorted(glob.glob(os.path.join(ROOT, "profiles", "*.txt")),
                                        key=os.path.getmtime, reverse=True)
     for p in paths:
         for line in open(p):
-            if line.startswith("TRAFFIC k_estimate"):
+            if line.startswith("TRAFFIC estimate_phase"):
                 fields = dict(f.split("=", 1) for f in line.split()[2:])
-                if fields.get("csrc_vate_hip_sha256_16") == cur:
+                if fields.get("kernel_src_sha256_16") == cur:
                     return float(fields["bytes_per_launch"]), os.path.relpath(p, ROOT)
     return None, None
 
@@ -113,7 +124,9 @@ def main() -> int:
 
     import torch
 
+    from paper_1812_00282_amd import learned as L
     from paper_1812_00282_amd import streams
+    from paper_1812_00282_amd import train as T
     from paper_1812_00282_amd.sketch import Config, Sketch
 
     wl = streams.LINK40G
@@ -127,7 +140,15 @@ def main() -> int:
     cfg = Config(wl.log2_pool, wl.width, wl.k, wl.g, seed_a=0xA5A5, seed_b=0x5A5A)
     sk = Sketch(cfg, device=dev)
     est = torch.empty(pop.n_hosts, dtype=torch.float32, device=dev)
-    out = (est, None, None)
+    est_cf = torch.empty(pop.n_hosts, dtype=torch.float32, device=dev)
+    if os.path.exists(T.WEIGHTS):
+        theta = T.load(device=dev)
+        weights_src = os.path.relpath(T.WEIGHTS, ROOT)
+    else:
+        theta = T.init_theta(0, dev)
+        weights_src = "untrained (zero output layer: equals the closed form)"
+    weights = L.pack(theta, L.new_weights(dev))
+    L.learned_workspace(sk, pop.n_hosts)
     torch.cuda.synchronize()
 
     def step(s, ev=None):
@@ -139,7 +160,7 @@ def main() -> int:
         sk.close_slice()                    # census
         if ev is not None:
             ev[2].record()
-        sk.estimate(hosts, out=out)         # all hosts, k' = k
+        L.estimate_learned(sk, hosts, weights, out=(est, est_cf), partitioned=True)
         if ev is not None:
             ev[3].record()
 
@@ -168,14 +189,14 @@ def main() -> int:
     est_ms = np.mean([e[2].elapsed_time(e[3]) for e in events])
     ms_per_step = elapsed * 1e3 / args.steps
 
-    # dominant kernel: the per-host estimate gather
-    bytes_per_host = 4 + wl.g * wl.width // 8 + 4
+    # dominant phase: the per-host estimate (VAT lookups + both estimates)
+    bytes_per_host = 4 + wl.g * wl.width // 8 + 8
     achieved = bytes_per_host * pop.n_hosts / (est_ms * 1e-3) / 1e9
     traffic, traffic_src = measured_traffic(args.profile_summary)
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                 "traffic_source": traffic_src,
-                "kernel": "k_estimate<8,false>",
+                "kernel": "estimate phase: k_part_scatter + k_part_lookup<8> + k_part_finalize_learned",
                 "algorithmic_bytes_per_launch": bytes_per_host * pop.n_hosts,
                 "avg_launch_ms": est_ms,
                 "random_lines_per_s": wl.g * pop.n_hosts / (est_ms * 1e-3)}
@@ -201,6 +222,10 @@ def main() -> int:
                       "estimate": est_ms},
         "roofline": roofline,
     }
+    log("[bench] learned vs closed form on held-out probe episodes")
+    bg = T.background(4, dev)
+    held = T.generate(T.HELD_OUT_SEEDS[:2], bg, device=dev)
+    line["learned_vs_closed_form"] = {"weights": weights_src, **T.evaluate(theta, held, device=dev)}
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(wl, pop, host_slices)

@@ -123,6 +123,34 @@ int vate_estimate(vate_sketch *s, const uint32_t *hosts_dev, size_t n_hosts,
                   uint32_t kprime, float *est_dev, uint32_t *live_dev,
                   uint32_t *hist_dev, void *stream);
 
+/* Device workspace (bytes) that vate_estimate_ws needs for n_hosts hosts:
+ * about 4*g bytes per host (one 32-bit entry per VAT) plus small tables.
+ * Errors: VATE_E_INVAL. */
+int vate_estimate_workspace_bytes(const vate_sketch *s, size_t n_hosts, size_t *bytes);
+
+/* Same results as vate_estimate (same outputs, layouts, errors; any k for the
+ * histogram), computed with the VAT lookups reordered for locality: the
+ * hosts' VATs are first written to the workspace grouped by pool slice of
+ * 2^20 ATs, then each slice's lookups are resolved against that slice of the
+ * activity bitmap held in LDS.  workspace_dev (256-byte aligned, at least
+ * vate_estimate_workspace_bytes) is scratch owned by the caller; calls that
+ * share a workspace must not overlap.  Errors: as vate_estimate, plus
+ * VATE_E_INVAL for a missing or small workspace. */
+int vate_estimate_ws(vate_sketch *s, const uint32_t *hosts_dev, size_t n_hosts,
+                     uint32_t kprime, float *est_dev, uint32_t *live_dev, uint32_t *hist_dev,
+                     void *workspace_dev, size_t workspace_bytes, void *stream);
+
+/* Estimates for several windows k'_1 < ... < k'_m (m <= 64, each in [1, k],
+ * given in host memory) from one pass over each host's VATs: any window up
+ * to k is answerable from the same state (Sec. 3, CheckAT; Sec. 4.1).
+ * est_dev receives n_hosts*m floats, row-major [host][window].  Lookups as in
+ * vate_estimate_ws; workspace from vate_estimate_multi_workspace_bytes.
+ * Errors: as vate_estimate_ws; VATE_E_INVAL for bad window lists. */
+int vate_estimate_multi_workspace_bytes(const vate_sketch *s, size_t n_hosts, size_t *bytes);
+int vate_estimate_multi_ws(vate_sketch *s, const uint32_t *hosts_dev, size_t n_hosts,
+                           const uint32_t *kprimes, uint32_t m, float *est_dev,
+                           void *workspace_dev, size_t workspace_bytes, void *stream);
+
 /* Pool census of the closed slice, copied to host memory: census_host[d] for
  * d < k counts ATs whose value is not 2k with distance d; census_host[k]
  * counts the rest (inactive for every k').  Synchronises `stream`.

@@ -4,11 +4,13 @@
  * Not part of the paper: a small network that reads a host's sketch state
  * and stands in for Eq. 11's closed form, which stays as its fallback and as
  * the judge of its error.  Features of a host, for a sketch with window k
- * (k + 2 <= 64), all at window k:
+ * (k + 3 <= 64), all at window k:
  *     x[d]   = hist[d] / g      d < k   (VATs at distance d, Eq. 5)
  *     x[k]   = live / g                 (active VATs)
  *     x[k+1] = 1 - Z_p                  (active fraction of the pool)
- *     x[k+2 .. 63] = 0
+ *     x[k+2] = r / 16                   (r below: the log of the closed form,
+ *                                        a function of live and Z_p)
+ *     x[k+3 .. 63] = 0
  * Network: z1 = W1 x + b1, a1 = GELU(z1), z2 = W2 a1 + b2, a2 = GELU(z2),
  * o = w3 . a2 + b3 + r with r = ln(max(closed-form estimate, 1)); the learned
  * estimate is exp(o).  GELU is 0.5 z (1 + erf(z / sqrt 2)).  Matrix products
@@ -67,7 +69,7 @@ int vate_mlp_fill(float *dst_dev, size_t count, float value, void *stream);
 /* Features and residual of n hosts from vate_estimate outputs: hist_dev
  * (n x (k+1) uint32, window k), est_dev (closed-form estimates at window k),
  * the pool's active fraction at window k.  Writes x_dev (bf16 [n][64]) and
- * r_dev (n floats).  Requires k + 2 <= 64. */
+ * r_dev (n floats).  Requires k + 3 <= 64. */
 int vate_mlp_features(const uint32_t *hist_dev, const float *est_dev, size_t n, uint32_t k,
                       uint32_t g, float pool_active_fraction, uint16_t *x_dev, float *r_dev,
                       void *stream);
@@ -76,10 +78,22 @@ int vate_mlp_features(const uint32_t *hist_dev, const float *est_dev, size_t n, 
  * the gather of vate_estimate (one pass over the VATs): est_cf_dev receives
  * the closed-form estimates, est_dev the learned ones (the closed form where
  * the network's output is not finite).  Requires a closed slice and
- * k + 2 <= 64.  Errors as vate_estimate, VATE_E_UNSUPPORTED for k > 62. */
+ * k + 3 <= 64.  Errors as vate_estimate, VATE_E_UNSUPPORTED for k > 61. */
 int vate_estimate_learned(vate_sketch *s, const uint32_t *hosts_dev, size_t n_hosts,
                           const void *weights_dev, float *est_dev, float *est_cf_dev,
                           void *stream);
+
+/* Workspace (bytes) for vate_estimate_learned_ws with n_hosts hosts: that of
+ * vate_estimate_ws plus one (k+1)-bin histogram per host. */
+int vate_estimate_learned_workspace_bytes(const vate_sketch *s, size_t n_hosts, size_t *bytes);
+
+/* Same outputs as vate_estimate_learned, with the VAT lookups of
+ * vate_estimate_ws (grouped by pool slice, resolved in LDS) and the network
+ * applied per 16-host tile afterwards.  workspace_dev: 256-byte aligned, at
+ * least vate_estimate_learned_workspace_bytes; caller-owned scratch. */
+int vate_estimate_learned_ws(vate_sketch *s, const uint32_t *hosts_dev, size_t n_hosts,
+                             const void *weights_dev, float *est_dev, float *est_cf_dev,
+                             void *workspace_dev, size_t workspace_bytes, void *stream);
 
 /* Diagnostic: D = A * B on the matrix cores for one 16x32 (A) by 32x16 (B)
  * tile, A and B row-major bf16, D row-major FP32 - checks the fragment

@@ -3,7 +3,7 @@
 Plain numpy in float64 with the GPU kernels' BF16 rounding points written
 out, so that the HIP forward/backward/Adam kernels can be compared with it:
 
-  features x (64) -> z1 = W1 x + b1 -> a1 = GELU(z1) -> z2 = W2 a1 + b2
+  features x (64; see features()) -> z1 = W1 x + b1 -> a1 = GELU(z1) -> z2 = W2 a1 + b2
   -> a2 = GELU(z2) -> o = w3 . a2 + b3 + r,     n_hat = exp(o)
 
 r is the log of the closed-form estimate (clamped below at 1), a fixed
@@ -160,12 +160,15 @@ def adam_step(p: Params, g: Params, st: AdamState, lr=1e-3, beta1=0.9, beta2=0.9
             setattr(st.m, name, m); setattr(st.v, name, v); setattr(p, name, theta)
 
 
-def features(hist: np.ndarray, live_k: np.ndarray, g: int, k: int, pool_occupancy: float) -> np.ndarray:
+def features(hist: np.ndarray, live_k: np.ndarray, g: int, k: int, pool_occupancy: float,
+             r: np.ndarray) -> np.ndarray:
     """(B, F) feature matrix from per-host distance histograms (B, k+1), live
-    counts at window k, and the pool's active fraction at window k."""
+    counts at window k, the pool's active fraction at window k, and
+    r = ln(max(closed-form estimate, 1)) (entered as r / 16)."""
     B = hist.shape[0]
     x = np.zeros((B, F), dtype=np.float64)
     x[:, :k] = hist[:, :k] / g
     x[:, k] = np.asarray(live_k, dtype=np.float64) / g
     x[:, k + 1] = pool_occupancy
+    x[:, k + 2] = np.asarray(r, dtype=np.float64) / 16.0
     return x

@@ -52,6 +52,10 @@ _SIGS = {
     "vate_close_slice": (_i32, [_vp, _vp]),
     "vate_estimate": (_i32, [_vp, _vp, _sz, _u32, _vp, _vp, _vp, _vp]),
     "vate_read_census": (_i32, [_vp, _vp, _vp]),
+    "vate_estimate_workspace_bytes": (_i32, [_vp, _sz, ctypes.POINTER(_sz)]),
+    "vate_estimate_ws": (_i32, [_vp, _vp, _sz, _u32, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "vate_estimate_multi_workspace_bytes": (_i32, [_vp, _sz, ctypes.POINTER(_sz)]),
+    "vate_estimate_multi_ws": (_i32, [_vp, _vp, _sz, _vp, _u32, _vp, _vp, _sz, _vp]),
     "vate_read_state": (_i32, [_vp, _vp, ctypes.POINTER(_u64), ctypes.POINTER(_u32),
                                ctypes.POINTER(_i32), _vp]),
     "vate_load_state": (_i32, [_vp, _vp, _u64, _u32, _i32, _vp]),
@@ -69,8 +73,32 @@ _SIGS = {
     "vate_mlp_fill": (_i32, [_vp, _sz, ctypes.c_float, _vp]),
     "vate_mlp_features": (_i32, [_vp, _vp, _sz, _u32, _u32, ctypes.c_float, _vp, _vp, _vp]),
     "vate_estimate_learned": (_i32, [_vp, _vp, _sz, _vp, _vp, _vp, _vp]),
+    "vate_estimate_learned_workspace_bytes": (_i32, [_vp, _sz, ctypes.POINTER(_sz)]),
+    "vate_estimate_learned_ws": (_i32, [_vp, _vp, _sz, _vp, _vp, _vp, _vp, _sz, _vp]),
     "vate_mlp_mfma_selftest": (_i32, [_vp, _vp, _vp, _vp]),
 }
+
+
+class VateBatchTune(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint32) for n in
+                ("ingest_tile", "census_tile", "estimate_block", "grid_preserve",
+                 "grid_ingest", "grid_census", "grid_estimate")]
+
+
+_SIGS.update({
+    # batched sketches (include/vate_batch.h)
+    "vate_batch_bytes": (_i32, [_u32, ctypes.POINTER(_sz)]),
+    "vate_batch_create": (_i32, [_vp, _u32, _vp, _vp, ctypes.POINTER(_vp)]),
+    "vate_batch_set_io": (_i32, [_vp, _u32, _vp, _u64, _vp, _u32, _u32, _vp, _vp]),
+    "vate_batch_slice": (_i32, [_vp, _vp]),
+    "vate_batch_capture": (_i32, [_vp, _vp]),
+    "vate_batch_replay": (_i32, [_vp, _vp]),
+    "vate_batch_get_tune": (_i32, [_vp, ctypes.POINTER(VateBatchTune)]),
+    "vate_batch_set_tune": (_i32, [_vp, ctypes.POINTER(VateBatchTune)]),
+    "vate_batch_autotune": (_i32, [_vp, _vp, ctypes.c_char_p, _sz]),
+    "vate_batch_last_error": (ctypes.c_char_p, [_vp]),
+    "vate_batch_destroy": (None, [_vp]),
+})
 
 MLP_FEATURES = 64
 MLP_HIDDEN = 64

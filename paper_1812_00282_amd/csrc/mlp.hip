@@ -254,13 +254,15 @@ __global__ void k_features(const uint32_t *__restrict__ hist, const float *__res
     }
     out[k] = bf16_bits((float)live / fg);
     out[k + 1] = bf16_bits(occupancy);
+    const float r = logf(fmaxf(est[h], 1.0f));
+    out[k + 2] = bf16_bits(r * 0.0625f);
     uint4 *dst = reinterpret_cast<uint4 *>(X + h * F);
     for (int j = 0; j < F / 8; ++j) {
         uint32_t wv[4];
         for (int t = 0; t < 4; ++t) wv[t] = (uint32_t)out[8 * j + 2 * t] | ((uint32_t)out[8 * j + 2 * t + 1] << 16);
         dst[j] = make_uint4(wv[0], wv[1], wv[2], wv[3]);
     }
-    R[h] = logf(fmaxf(est[h], 1.0f));
+    R[h] = r;
 }
 
 __global__ void k_fill(float *__restrict__ p, int count, float value)
@@ -355,7 +357,7 @@ int vate_mlp_features(const uint32_t *hist_dev, const float *est_dev, size_t n, 
                       float pool_active_fraction, uint16_t *x_dev, float *r_dev, void *stream)
 {
     if (n == 0) return VATE_OK;
-    if (k < 1 || k + 2 > (uint32_t)F) return VATE_E_UNSUPPORTED;
+    if (k < 1 || k + 3 > (uint32_t)F) return VATE_E_UNSUPPORTED;
     if (!hist_dev || !est_dev || !x_dev || !r_dev || g < 1 || (reinterpret_cast<uintptr_t>(x_dev) & 15u))
         return VATE_E_INVAL;
     const uint64_t blocks = (n + 255) / 256;

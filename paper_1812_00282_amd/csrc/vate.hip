@@ -14,11 +14,13 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <string>
 
 #include "vate.h"
 #include "vate_core.h"
 #include "vate_mlp.h"
 #include "mlp_core.h"
+#include "vate_batch.h"
 
 namespace vate {
 
@@ -252,6 +254,43 @@ __device__ __forceinline__ void store_bits(uint8_t *__restrict__ bitmap, uint64_
         bitmap[ch] = (uint8_t)bits;                                  // 8 ATs per chunk
 }
 
+// One 16-byte chunk of the census: returns the chunk's activity bits and adds
+// each active AT's distance to hist (LDS counters) or, without LDS, directly
+// to the sketch's census.
+template <int W>
+__device__ __forceinline__ uint32_t census_chunk(const Geo &G, const uint4 &v, uint64_t ch, uint32_t bact0,
+                                                 uint32_t *hist, unsigned long long *census)
+{
+    constexpr uint32_t E = 128 / W;
+    const uint32_t pat = replicate<W>(G.twok);
+    if (v.x == pat && v.y == pat && v.z == pat && v.w == pat) return 0;
+    uint32_t bits = 0;
+    const uint64_t p0 = ch * E;
+    uint32_t bid0 = 0, act0 = 0;
+    uint64_t next = 0;
+    if (G.fast_blocks) {
+        bid0 = block_of(G, (uint32_t)p0);
+        act0 = block_act(G, bact0, bid0);
+        next = block_start(G, bid0 + 1);
+    }
+    for (uint32_t e = 0; e < E; ++e) {
+        uint32_t val = chunk_get<W>(v, e);
+        if (val == G.twok) continue;
+        uint32_t act;
+        if (G.fast_blocks)
+            act = p0 + e < next ? act0 : block_act(G, bact0, bid0 + 1);
+        else
+            act = block_act(G, bact0, block_of(G, (uint32_t)(p0 + e)));
+        uint32_t d = at_dist(G, act, val);
+        if (d < G.k) {
+            bits |= 1u << e;
+            if (hist) atomicAdd(&hist[d], 1u);
+            else atomicAdd(&census[d], 1ull);
+        }
+    }
+    return bits;
+}
+
 template <int W>
 __global__ void __launch_bounds__(256) k_census(Geo G, const uint4 *__restrict__ pool4, uint64_t nchunks,
                                                 DevState *__restrict__ st, uint8_t *__restrict__ bitmap)
@@ -263,7 +302,6 @@ __global__ void __launch_bounds__(256) k_census(Geo G, const uint4 *__restrict__
     __syncthreads();
     const uint32_t bact0 = st->bact0;
     const uint32_t pat = replicate<W>(G.twok);
-    constexpr uint32_t E = 128 / W;
     constexpr int U = 4;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t c0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c0 < nchunks; c0 += U * stride) {
@@ -277,33 +315,7 @@ __global__ void __launch_bounds__(256) k_census(Geo G, const uint4 *__restrict__
         for (int u = 0; u < U; ++u) {
             const uint64_t ch = c0 + u * stride;
             if (ch >= nchunks) continue;
-            uint32_t bits = 0;
-            if (!(v[u].x == pat && v[u].y == pat && v[u].z == pat && v[u].w == pat)) {
-                const uint64_t p0 = ch * E;
-                uint32_t bid0 = 0, act0 = 0;
-                uint64_t next = 0;
-                if (G.fast_blocks) {
-                    bid0 = block_of(G, (uint32_t)p0);
-                    act0 = block_act(G, bact0, bid0);
-                    next = block_start(G, bid0 + 1);
-                }
-                for (uint32_t e = 0; e < E; ++e) {
-                    uint32_t val = chunk_get<W>(v[u], e);
-                    if (val == G.twok) continue;
-                    uint32_t act;
-                    if (G.fast_blocks)
-                        act = p0 + e < next ? act0 : block_act(G, bact0, bid0 + 1);
-                    else
-                        act = block_act(G, bact0, block_of(G, (uint32_t)(p0 + e)));
-                    uint32_t d = at_dist(G, act, val);
-                    if (d < G.k) {
-                        bits |= 1u << e;
-                        if (lds) atomicAdd(&hist[d], 1u);
-                        else atomicAdd(&census_of(st)[d], 1ull);
-                    }
-                }
-            }
-            store_bits<W>(bitmap, ch, bits);
+            store_bits<W>(bitmap, ch, census_chunk<W>(G, v[u], ch, bact0, lds ? hist : nullptr, census_of(st)));
         }
     }
     __syncthreads();
@@ -428,7 +440,7 @@ __global__ void __launch_bounds__(256) k_estimate(Geo G, const uint8_t *__restri
 // tiles built straight from the LDS histograms; the closed form is kept as
 // the output where the network's result is not finite.
 // ---------------------------------------------------------------------------
-constexpr int kLearnMaxK = VATE_MLP_FEATURES - 2;
+constexpr int kLearnMaxK = VATE_MLP_FEATURES - 3;
 
 template <int W>
 __global__ void __launch_bounds__(256) k_estimate_learned(Geo G, const uint8_t *__restrict__ pool,
@@ -490,6 +502,8 @@ __global__ void __launch_bounds__(256) k_estimate_learned(Geo G, const uint8_t *
                 x = (float)my[rows * 65 + host] / fg;
             else if (f == (int)G.k + 1)
                 x = occupancy;
+            else if (f == (int)G.k + 2)
+                x = logf(fmaxf(cf_all[wave][host], 1.0f)) * 0.0625f;
             xs[m * mlp::LDS_STRIDE + f] = mlp::bf16_bits(x);
         }
         __syncthreads();
@@ -509,6 +523,243 @@ __global__ void __launch_bounds__(256) k_estimate_learned(Geo G, const uint8_t *
         }
         __syncthreads();
     }
+}
+
+// ---------------------------------------------------------------------------
+// Partitioned estimate.  The direct gather above touches one random cache
+// line per VAT anywhere in the bitmap, so every VAT costs a line fill from
+// beyond L2.  Here the same CheckAT lookups are reordered for locality:
+//
+//  k_part_scatter: a workgroup hashes the g VATs of its 256 hosts twice:
+//    first counting them per pool slice (2^20 ATs, i.e. a 128 KiB bitmap
+//    slice), then writing one 32-bit entry (host within the workgroup, AT
+//    within the slice) per VAT into the workgroup's own region of the
+//    workspace, grouped by slice.  Regions are fixed (256 g entries), so no
+//    global scan or atomics are needed; per-slice counts and offsets of each
+//    region are stored beside it.
+//  k_part_lookup: a workgroup owns one slice: it loads the slice of the
+//    activity bitmap into LDS and streams the entries of that slice from all
+//    regions, resolving each with an LDS read.  Only the rare active VATs go
+//    further (AT value for the distance when needed, atomic add into the
+//    host's live count and histogram).
+//  k_part_finalize: per host, Eq. 11 from the counts.
+//
+// HBM traffic per host is about 8 g bytes of streamed entries (written once,
+// read once) instead of g random line fills.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kSliceLog2 = 20;                 // ATs per slice = 2^20
+constexpr uint32_t kPartHosts = 256;                // hosts per scatter workgroup
+constexpr uint32_t kLookupThreads = 1024;
+constexpr uint32_t kMaxSlices = 4096;               // 2^32 / 2^20
+
+struct PartGeo {
+    uint32_t slice_log2;     // min(c, 20)
+    uint32_t n_slices;       // N >> slice_log2
+    uint32_t n_groups;       // ceil(n_hosts / 256)
+    uint32_t reps;           // lookup workgroups per slice
+    uint64_t region;         // entries per group region = 256 g
+};
+
+__global__ void __launch_bounds__(kPartHosts) k_part_scatter(Geo G, PartGeo PG,
+                                                            const uint32_t *__restrict__ hosts, uint32_t n,
+                                                            uint32_t *__restrict__ entries,
+                                                            uint32_t *__restrict__ cnt_out,
+                                                            uint32_t *__restrict__ off_out)
+{
+    __shared__ uint32_t cnt[kMaxSlices];
+    __shared__ uint32_t cur[kMaxSlices];
+    const uint32_t ns = PG.n_slices, sl = PG.slice_log2;
+    for (uint32_t b = threadIdx.x; b < ns; b += blockDim.x) cnt[b] = 0;
+    __syncthreads();
+    const uint32_t h = blockIdx.x * kPartHosts + threadIdx.x;
+    const bool valid = h < n;
+    const uint32_t key = host_key(G, valid ? hosts[h] : 0u);
+    if (valid)
+        for (uint32_t i = 0; i < G.g; ++i) atomicAdd(&cnt[vat_pid(G, key, i) >> sl], 1u);
+    __syncthreads();
+    // exclusive prefix over slices (one thread; ns <= 4096 and this runs once per group)
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (uint32_t b = 0; b < ns; ++b) {
+            cur[b] = run;
+            run += cnt[b];
+        }
+    }
+    __syncthreads();
+    for (uint32_t b = threadIdx.x; b < ns; b += blockDim.x) {
+        cnt_out[(size_t)blockIdx.x * ns + b] = cnt[b];
+        off_out[(size_t)blockIdx.x * ns + b] = cur[b];
+    }
+    __syncthreads();
+    uint32_t *region = entries + (size_t)blockIdx.x * PG.region;
+    const uint32_t mask = (1u << sl) - 1u;
+    if (valid)
+        for (uint32_t i = 0; i < G.g; ++i) {
+            const uint32_t pid = vat_pid(G, key, i);
+            const uint32_t slot = atomicAdd(&cur[pid >> sl], 1u);
+            region[slot] = (threadIdx.x << sl) | (pid & mask);
+        }
+}
+
+template <int W>
+__global__ void __launch_bounds__(kLookupThreads) k_part_lookup(Geo G, PartGeo PG, const uint8_t *__restrict__ pool,
+                                                               const DevState *__restrict__ st,
+                                                               const uint8_t *__restrict__ bitmap,
+                                                               const uint32_t *__restrict__ entries,
+                                                               const uint32_t *__restrict__ cnt_in,
+                                                               const uint32_t *__restrict__ off_in,
+                                                               uint32_t n, uint32_t kprime,
+                                                               uint32_t *__restrict__ live,
+                                                               uint32_t *__restrict__ hist)
+{
+    extern __shared__ uint32_t bits[];     // the slice's bitmap, 2^slice_log2 bits
+    const uint32_t b = blockIdx.x / PG.reps, rep = blockIdx.x % PG.reps;
+    const uint32_t sl = PG.slice_log2, mask = (1u << sl) - 1u;
+    const uint32_t words = ((1u << sl) + 31) / 32;
+    const uint32_t *src = reinterpret_cast<const uint32_t *>(bitmap) + (size_t)b * words;
+    for (uint32_t i = threadIdx.x; i < words; i += blockDim.x) bits[i] = src[i];
+    __syncthreads();
+    const uint32_t bact0 = st->bact0;
+    const bool need_dist = hist != nullptr || kprime < G.k;
+    const uint32_t base_pid = b << sl;
+    for (uint32_t grp = rep; grp < PG.n_groups; grp += PG.reps) {
+        const uint32_t cnt = cnt_in[(size_t)grp * PG.n_slices + b];
+        const uint32_t *e = entries + (size_t)grp * PG.region + off_in[(size_t)grp * PG.n_slices + b];
+        for (uint32_t j = threadIdx.x; j < cnt; j += blockDim.x) {
+            const uint32_t ent = e[j];
+            const uint32_t local = ent & mask;
+            if (!((bits[local >> 5] >> (local & 31u)) & 1u)) continue;
+            const uint32_t host = grp * kPartHosts + (ent >> sl);
+            if (!need_dist) {
+                atomicAdd(&live[host], 1u);
+                continue;
+            }
+            const uint32_t pid = base_pid | local;
+            const uint32_t d = at_dist(G, block_act(G, bact0, block_of(G, pid)), load_at<W>(pool, pid));
+            if (d < kprime) atomicAdd(&live[host], 1u);
+            if (hist) atomicAdd(&hist[(size_t)host * (G.k + 1) + d], 1u);
+        }
+    }
+    (void)n;
+}
+
+__global__ void k_part_finalize(Geo G, const DevState *__restrict__ st, uint32_t n, uint32_t kprime,
+                                const uint32_t *__restrict__ live, float *__restrict__ est,
+                                uint32_t *__restrict__ live_out, uint32_t *__restrict__ hist)
+{
+    const uint64_t active_pool = pool_active(st, kprime);
+    const uint32_t h = blockIdx.x * blockDim.x + threadIdx.x;
+    if (h >= n) return;
+    const uint32_t lv = live[h];
+    est[h] = estimate_from_counts(G.g - lv, G.N - active_pool, G.g, G.c);
+    if (live_out) live_out[h] = lv;
+    if (hist) {
+        uint32_t *row = hist + (size_t)h * (G.k + 1);
+        uint32_t s = 0;
+        for (uint32_t d = 0; d < G.k; ++d) s += row[d];
+        row[G.k] = G.g - s;
+    }
+}
+
+// Learned estimate after the partitioned lookups (window k): per wavefront 16
+// hosts' features are built from their histogram rows, run through the
+// network on the matrix cores, and both estimates are written.
+__global__ void __launch_bounds__(256) k_part_finalize_learned(Geo G, const DevState *__restrict__ st, uint32_t n,
+                                                               const uint32_t *__restrict__ live,
+                                                               const uint32_t *__restrict__ hist,
+                                                               const mlp::Packed *__restrict__ P,
+                                                               float *__restrict__ est, float *__restrict__ cf_out)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t xs_all[4][16 * mlp::LDS_STRIDE];
+    __shared__ __attribute__((aligned(16))) uint16_t a1_all[4][16 * mlp::LDS_STRIDE];
+    __shared__ float cf_all[4][16];
+    const uint64_t active_pool = pool_active(st, G.k);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63, q = l >> 4, c = l & 15;
+    const uint32_t h0 = blockIdx.x * 64 + 16 * w;
+    const float fg = (float)G.g, occupancy = (float)active_pool / (float)G.N;
+    if (l < 16) {
+        const uint32_t h = h0 + l;
+        const float cf = h < n ? estimate_from_counts(G.g - live[h], G.N - active_pool, G.g, G.c) : 0.f;
+        cf_all[w][l] = cf;
+        if (h < n) cf_out[h] = cf;
+    }
+    __syncthreads();
+    uint16_t *xs = xs_all[w];
+    for (int e = l; e < 16 * VATE_MLP_FEATURES; e += 64) {
+        const int m = e >> 6, f = e & 63;
+        const uint32_t h = h0 + m;
+        float x = 0.f;
+        if (h < n) {
+            if (f < (int)G.k)
+                x = (float)hist[(size_t)h * (G.k + 1) + f] / fg;
+            else if (f == (int)G.k)
+                x = (float)live[h] / fg;
+            else if (f == (int)G.k + 1)
+                x = occupancy;
+            else if (f == (int)G.k + 2)
+                x = logf(fmaxf(cf_all[w][m], 1.0f)) * 0.0625f;
+        }
+        xs[m * mlp::LDS_STRIDE + f] = mlp::bf16_bits(x);
+    }
+    __syncthreads();
+    float r4[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) r4[r] = logf(fmaxf(cf_all[w][4 * q + r], 1.0f));
+    mlp::f32x4 z1[4], z2[4];
+    float a2v[4][4], o4[4];
+    mlp::forward16(P, xs, a1_all[w], r4, z1, z2, a2v, o4);
+    if (c < 4) {
+        const uint32_t h = h0 + 4 * q + c;
+        if (h < n) {
+            const float ex = expf(o4[c]);
+            est[h] = isfinite(ex) ? ex : cf_all[w][4 * q + c];
+        }
+    }
+}
+
+// Several windows from one pass: the pool's active count for every window
+// (prefix of the census), then per host the prefix of its distance histogram
+// gives live(k') for each requested k' (ascending), and Eq. 11 for each.
+constexpr uint32_t kMaxWindows = 64;
+
+struct Windows {
+    uint32_t m;
+    uint32_t kp[kMaxWindows];
+};
+
+__global__ void k_census_prefix(Geo G, const DevState *__restrict__ st, unsigned long long *__restrict__ cum)
+{
+    if (threadIdx.x == 0) {
+        unsigned long long run = 0;
+        cum[0] = 0;
+        for (uint32_t d = 0; d < G.k; ++d) {
+            run += census_of(st)[d];
+            cum[d + 1] = run;
+        }
+    }
+}
+
+__global__ void k_part_finalize_multi(Geo G, uint32_t n, Windows win, const unsigned long long *__restrict__ cum,
+                                      const uint32_t *__restrict__ hist, float *__restrict__ est)
+{
+    const uint32_t h = blockIdx.x * blockDim.x + threadIdx.x;
+    if (h >= n) return;
+    const uint32_t *row = hist + (size_t)h * (G.k + 1);
+    uint32_t live = 0, j = 0;
+    for (uint32_t d = 0; d < G.k && j < win.m; ++d) {
+        live += row[d];
+        while (j < win.m && win.kp[j] == d + 1) {
+            est[(size_t)h * win.m + j] = estimate_from_counts(G.g - live, G.N - cum[d + 1], G.g, G.c);
+            ++j;
+        }
+    }
+}
+
+__global__ void k_fill_u32(uint32_t *__restrict__ p, uint64_t count)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
 }
 
 // ---------------------------------------------------------------------------
@@ -541,18 +792,16 @@ __global__ void k_set_clock(Geo G, DevState *__restrict__ st, unsigned long long
 // blocks belongs to the i0 pass), which rewrites it only if an AT changed.
 // ---------------------------------------------------------------------------
 template <int W>
-__global__ void __launch_bounds__(256) k_preserve(Geo G, uint4 *__restrict__ pool4,
-                                                  const DevState *__restrict__ st, uint64_t max_chunks)
+__device__ __forceinline__ void preserve_chunk(const Geo &G, uint4 *__restrict__ pool4, uint32_t bact0, uint64_t j,
+                                               uint64_t max_chunks)
 {
     constexpr uint64_t E = 128 / W;
-    const uint32_t bact0 = st->bact0;
     const uint32_t i0 = bact0 == 0 ? 0 : G.twok - bact0;                        // (BACT^0 + i0) mod 2k == 0
     const uint32_t i1 = bact0 <= G.k ? G.k - bact0 : G.twok + G.k - bact0;      // == k
     const uint64_t s0 = block_start(G, i0), e0 = block_start(G, i0 + 1);
     const uint64_t s1 = block_start(G, i1), e1 = block_start(G, i1 + 1);
     const uint64_t c0lo = s0 / E, c0hi = s0 < e0 ? (e0 + E - 1) / E : c0lo;
     const uint64_t c1lo = s1 / E, c1hi = s1 < e1 ? (e1 + E - 1) / E : c1lo;
-    const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool second = j >= max_chunks;
     const uint64_t ch = second ? c1lo + (j - max_chunks) : c0lo + j;
     if (j >= 2 * max_chunks) return;
@@ -577,6 +826,15 @@ __global__ void __launch_bounds__(256) k_preserve(Geo G, uint4 *__restrict__ poo
     }
     if (changed) pool4[ch] = v;
 }
+
+template <int W>
+__global__ void __launch_bounds__(256) k_preserve(Geo G, uint4 *__restrict__ pool4,
+                                                  const DevState *__restrict__ st, uint64_t max_chunks)
+{
+    preserve_chunk<W>(G, pool4, st->bact0, (uint64_t)blockIdx.x * blockDim.x + threadIdx.x, max_chunks);
+}
+
+#include "vate_batch_kernels.h"
 
 }  // namespace vate
 
@@ -707,7 +965,78 @@ static void launch_estimate_learned(vate_sketch *s, const uint32_t *hosts, uint3
         s->G, s->pool, s->st, s->bitmap, hosts, n, static_cast<const mlp::Packed *>(weights), est, cf);
 }
 
+// ---- partitioned estimate: workspace layout and launches ----
+static PartGeo part_geo(const vate_sketch *s, uint64_t n)
+{
+    PartGeo pg;
+    pg.slice_log2 = s->G.c < kSliceLog2 ? s->G.c : kSliceLog2;
+    pg.n_slices = (uint32_t)(s->G.N >> pg.slice_log2);
+    pg.n_groups = (uint32_t)((n + kPartHosts - 1) / kPartHosts);
+    pg.region = (uint64_t)kPartHosts * s->G.g;
+    // enough lookup workgroups to cover every CU about twice
+    uint32_t reps = (512 + pg.n_slices - 1) / pg.n_slices;
+    if (reps > pg.n_groups) reps = pg.n_groups;
+    pg.reps = reps < 1 ? 1 : reps;
+    return pg;
+}
+
+struct PartWs {
+    uint32_t *entries, *cnt, *off, *live;
+    size_t bytes;
+};
+
+static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+static PartWs part_ws(const PartGeo &pg, uint64_t n, void *base)
+{
+    PartWs w;
+    uint8_t *p = static_cast<uint8_t *>(base);
+    size_t off = 0;
+    w.entries = reinterpret_cast<uint32_t *>(p + off);
+    off += align256((size_t)pg.n_groups * pg.region * 4);
+    w.cnt = reinterpret_cast<uint32_t *>(p + off);
+    off += align256((size_t)pg.n_groups * pg.n_slices * 4);
+    w.off = reinterpret_cast<uint32_t *>(p + off);
+    off += align256((size_t)pg.n_groups * pg.n_slices * 4);
+    w.live = reinterpret_cast<uint32_t *>(p + off);
+    off += align256((size_t)n * 4);
+    w.bytes = off;
+    return w;
+}
+
+template <int W>
+static int launch_estimate_part(vate_sketch *s, const uint32_t *hosts, uint32_t n, uint32_t kprime, float *est,
+                                uint32_t *live, uint32_t *hist, void *ws, hipStream_t st,
+                                const void *weights = nullptr, float *cf = nullptr)
+{
+    const PartGeo pg = part_geo(s, n);
+    const PartWs w = part_ws(pg, n, ws);
+    if (weights) hist = reinterpret_cast<uint32_t *>(static_cast<uint8_t *>(ws) + w.bytes);
+    const uint32_t words = ((1u << pg.slice_log2) + 31) / 32;
+    const size_t lds = (size_t)words * 4;
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_part_lookup<W>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)(4u << kSliceLog2 >> 5));
+        if (e != hipSuccess) return fail(s, VATE_E_DEVICE, hipGetErrorString(e));
+        attr_set = true;
+    }
+    k_fill_u32<<<grid_for(n, 256, 4096), 256, 0, st>>>(w.live, n);
+    if (hist) k_fill_u32<<<grid_for((uint64_t)n * (s->G.k + 1), 256, 8192), 256, 0, st>>>(hist, (uint64_t)n * (s->G.k + 1));
+    k_part_scatter<<<pg.n_groups, kPartHosts, 0, st>>>(s->G, pg, hosts, n, w.entries, w.cnt, w.off);
+    k_part_lookup<W><<<pg.n_slices * pg.reps, kLookupThreads, lds, st>>>(s->G, pg, s->pool, s->st, s->bitmap,
+                                                                        w.entries, w.cnt, w.off, n, kprime,
+                                                                        w.live, hist);
+    if (weights)
+        k_part_finalize_learned<<<grid_for(n, 64, 1u << 30), 256, 0, st>>>(
+            s->G, s->st, n, w.live, hist, static_cast<const mlp::Packed *>(weights), est, cf);
+    else
+        k_part_finalize<<<grid_for(n, 256, 1u << 30), 256, 0, st>>>(s->G, s->st, n, kprime, w.live, est, live, hist);
+    return VATE_OK;
+}
+
 extern "C" {
+int vate_estimate_learned_workspace_bytes(const vate_sketch *s, size_t n_hosts, size_t *bytes);
 
 int vate_state_bytes(const vate_params *p, size_t *pool_bytes, size_t *state_bytes)
 {
@@ -815,13 +1144,140 @@ int vate_estimate(vate_sketch *s, const uint32_t *hosts_dev, size_t n_hosts, uin
     return check_launch(s, "estimate");
 }
 
+int vate_estimate_workspace_bytes(const vate_sketch *s, size_t n_hosts, size_t *bytes)
+{
+    if (!s || !bytes) return VATE_E_INVAL;
+    if (n_hosts > 0xFFFFFFFFull - 1024) return VATE_E_INVAL;
+    const PartGeo pg = part_geo(s, n_hosts);
+    *bytes = part_ws(pg, n_hosts, nullptr).bytes;
+    return VATE_OK;
+}
+
+int vate_estimate_ws(vate_sketch *s, const uint32_t *hosts_dev, size_t n_hosts, uint32_t kprime, float *est_dev,
+                     uint32_t *live_dev, uint32_t *hist_dev, void *workspace_dev, size_t workspace_bytes,
+                     void *stream)
+{
+    if (!s) return VATE_E_INVAL;
+    if (s->dead) return VATE_E_DEVICE;
+    if (!s->closed) return fail(s, VATE_E_STATE, "estimate needs a closed slice (call vate_close_slice)");
+    if (kprime < 1 || kprime > s->p.k) return fail(s, VATE_E_INVAL, "k' must be in [1, k]");
+    if (n_hosts > 0xFFFFFFFFull - 1024) return fail(s, VATE_E_INVAL, "too many hosts");
+    if (n_hosts == 0) return VATE_OK;
+    size_t need = 0;
+    vate_estimate_workspace_bytes(s, n_hosts, &need);
+    if (!workspace_dev || workspace_bytes < need || (reinterpret_cast<uintptr_t>(workspace_dev) & 255u))
+        return fail(s, VATE_E_INVAL, "workspace missing, too small or not 256-byte aligned");
+    if (!hosts_dev || !est_dev || (reinterpret_cast<uintptr_t>(hosts_dev) & 3u) ||
+        (reinterpret_cast<uintptr_t>(est_dev) & 3u) || (reinterpret_cast<uintptr_t>(live_dev) & 3u) ||
+        (reinterpret_cast<uintptr_t>(hist_dev) & 3u))
+        return fail(s, VATE_E_INVAL, "hosts/est/live/hist must be non-NULL (live, hist may be NULL) and 4-byte aligned");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const uint32_t n = (uint32_t)n_hosts;
+    int rc;
+    if (s->p.width == 4) rc = launch_estimate_part<4>(s, hosts_dev, n, kprime, est_dev, live_dev, hist_dev, workspace_dev, st);
+    else if (s->p.width == 8) rc = launch_estimate_part<8>(s, hosts_dev, n, kprime, est_dev, live_dev, hist_dev, workspace_dev, st);
+    else rc = launch_estimate_part<16>(s, hosts_dev, n, kprime, est_dev, live_dev, hist_dev, workspace_dev, st);
+    if (rc != VATE_OK) return rc;
+    return check_launch(s, "estimate_ws");
+}
+
+int vate_estimate_learned_ws(vate_sketch *s, const uint32_t *hosts_dev, size_t n_hosts, const void *weights_dev,
+                             float *est_dev, float *est_cf_dev, void *workspace_dev, size_t workspace_bytes,
+                             void *stream)
+{
+    if (!s) return VATE_E_INVAL;
+    if (s->dead) return VATE_E_DEVICE;
+    if (!s->closed) return fail(s, VATE_E_STATE, "estimate needs a closed slice (call vate_close_slice)");
+    if (s->p.k > (uint32_t)kLearnMaxK) return fail(s, VATE_E_UNSUPPORTED, "learned estimator needs k + 3 <= 64");
+    if (n_hosts > 0xFFFFFFFFull - 1024) return fail(s, VATE_E_INVAL, "too many hosts");
+    if (n_hosts == 0) return VATE_OK;
+    size_t need = 0;
+    vate_estimate_learned_workspace_bytes(s, n_hosts, &need);
+    if (!workspace_dev || workspace_bytes < need || (reinterpret_cast<uintptr_t>(workspace_dev) & 255u))
+        return fail(s, VATE_E_INVAL, "workspace missing, too small or not 256-byte aligned");
+    if (!hosts_dev || !est_dev || !est_cf_dev || !weights_dev || (reinterpret_cast<uintptr_t>(hosts_dev) & 3u) ||
+        (reinterpret_cast<uintptr_t>(est_dev) & 3u) || (reinterpret_cast<uintptr_t>(est_cf_dev) & 3u) ||
+        (reinterpret_cast<uintptr_t>(weights_dev) & 255u))
+        return fail(s, VATE_E_INVAL, "hosts/est/est_cf must be 4-byte and weights 256-byte aligned, non-NULL");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const uint32_t n = (uint32_t)n_hosts;
+    const uint32_t k = s->p.k;
+    int rc;
+    if (s->p.width == 4) rc = launch_estimate_part<4>(s, hosts_dev, n, k, est_dev, nullptr, nullptr, workspace_dev, st, weights_dev, est_cf_dev);
+    else if (s->p.width == 8) rc = launch_estimate_part<8>(s, hosts_dev, n, k, est_dev, nullptr, nullptr, workspace_dev, st, weights_dev, est_cf_dev);
+    else rc = launch_estimate_part<16>(s, hosts_dev, n, k, est_dev, nullptr, nullptr, workspace_dev, st, weights_dev, est_cf_dev);
+    if (rc != VATE_OK) return rc;
+    return check_launch(s, "estimate_learned_ws");
+}
+
+int vate_estimate_multi_workspace_bytes(const vate_sketch *s, size_t n_hosts, size_t *bytes)
+{
+    if (!s || !bytes) return VATE_E_INVAL;
+    if (n_hosts > 0xFFFFFFFFull - 1024) return VATE_E_INVAL;
+    const PartGeo pg = part_geo(s, n_hosts);
+    *bytes = part_ws(pg, n_hosts, nullptr).bytes + align256((size_t)n_hosts * (s->p.k + 1) * 4) +
+             align256(8ull * (s->p.k + 1));
+    return VATE_OK;
+}
+
+int vate_estimate_multi_ws(vate_sketch *s, const uint32_t *hosts_dev, size_t n_hosts, const uint32_t *kprimes,
+                           uint32_t m, float *est_dev, void *workspace_dev, size_t workspace_bytes, void *stream)
+{
+    if (!s) return VATE_E_INVAL;
+    if (s->dead) return VATE_E_DEVICE;
+    if (!s->closed) return fail(s, VATE_E_STATE, "estimate needs a closed slice (call vate_close_slice)");
+    if (!kprimes || m < 1 || m > kMaxWindows) return fail(s, VATE_E_INVAL, "need 1..64 windows");
+    Windows win;
+    win.m = m;
+    for (uint32_t j = 0; j < m; ++j) {
+        if (kprimes[j] < 1 || kprimes[j] > s->p.k || (j > 0 && kprimes[j] <= kprimes[j - 1]))
+            return fail(s, VATE_E_INVAL, "windows must be ascending, distinct and in [1, k]");
+        win.kp[j] = kprimes[j];
+    }
+    if (n_hosts > 0xFFFFFFFFull - 1024) return fail(s, VATE_E_INVAL, "too many hosts");
+    if (n_hosts == 0) return VATE_OK;
+    size_t need = 0;
+    vate_estimate_multi_workspace_bytes(s, n_hosts, &need);
+    if (!workspace_dev || workspace_bytes < need || (reinterpret_cast<uintptr_t>(workspace_dev) & 255u))
+        return fail(s, VATE_E_INVAL, "workspace missing, too small or not 256-byte aligned");
+    if (!hosts_dev || !est_dev || (reinterpret_cast<uintptr_t>(hosts_dev) & 3u) ||
+        (reinterpret_cast<uintptr_t>(est_dev) & 3u))
+        return fail(s, VATE_E_INVAL, "hosts/est must be non-NULL and 4-byte aligned");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const uint32_t n = (uint32_t)n_hosts;
+    const PartGeo pg = part_geo(s, n);
+    const size_t base = part_ws(pg, n, nullptr).bytes;
+    uint8_t *ws = static_cast<uint8_t *>(workspace_dev);
+    uint32_t *hist = reinterpret_cast<uint32_t *>(ws + base);
+    unsigned long long *cum =
+        reinterpret_cast<unsigned long long *>(ws + base + align256((size_t)n * (s->p.k + 1) * 4));
+    int rc;
+    // the lookups for window k fill the per-host histograms (est is scratch here)
+    if (s->p.width == 4) rc = launch_estimate_part<4>(s, hosts_dev, n, s->p.k, est_dev, nullptr, hist, ws, st);
+    else if (s->p.width == 8) rc = launch_estimate_part<8>(s, hosts_dev, n, s->p.k, est_dev, nullptr, hist, ws, st);
+    else rc = launch_estimate_part<16>(s, hosts_dev, n, s->p.k, est_dev, nullptr, hist, ws, st);
+    if (rc != VATE_OK) return rc;
+    k_census_prefix<<<1, 64, 0, st>>>(s->G, s->st, cum);
+    k_part_finalize_multi<<<grid_for(n, 256, 1u << 30), 256, 0, st>>>(s->G, n, win, cum, hist, est_dev);
+    return check_launch(s, "estimate_multi_ws");
+}
+
+int vate_estimate_learned_workspace_bytes(const vate_sketch *s, size_t n_hosts, size_t *bytes)
+{
+    if (!s || !bytes) return VATE_E_INVAL;
+    if (n_hosts > 0xFFFFFFFFull - 1024) return VATE_E_INVAL;
+    const PartGeo pg = part_geo(s, n_hosts);
+    *bytes = part_ws(pg, n_hosts, nullptr).bytes + align256((size_t)n_hosts * (s->p.k + 1) * 4);
+    return VATE_OK;
+}
+
 int vate_estimate_learned(vate_sketch *s, const uint32_t *hosts_dev, size_t n_hosts, const void *weights_dev,
                           float *est_dev, float *est_cf_dev, void *stream)
 {
     if (!s) return VATE_E_INVAL;
     if (s->dead) return VATE_E_DEVICE;
     if (!s->closed) return fail(s, VATE_E_STATE, "estimate needs a closed slice (call vate_close_slice)");
-    if (s->p.k > (uint32_t)kLearnMaxK) return fail(s, VATE_E_UNSUPPORTED, "learned estimator needs k + 2 <= 64");
+    if (s->p.k > (uint32_t)kLearnMaxK) return fail(s, VATE_E_UNSUPPORTED, "learned estimator needs k + 3 <= 64");
     if (n_hosts > 0xFFFFFFFFull - 1024) return fail(s, VATE_E_INVAL, "too many hosts");
     if (n_hosts == 0) return VATE_OK;
     if (!hosts_dev || !est_dev || !est_cf_dev || !weights_dev || (reinterpret_cast<uintptr_t>(hosts_dev) & 3u) ||
@@ -931,3 +1387,5 @@ uint32_t vate_host_block(const vate_params *p, uint64_t pid)
 }
 
 }  // extern "C"
+
+#include "vate_batch_api.h"

@@ -6,6 +6,8 @@ int16 tensors holding bf16 bit patterns, [n][64].
 """
 from __future__ import annotations
 
+import ctypes
+
 import numpy as np
 import torch
 
@@ -79,8 +81,21 @@ def features(hist: torch.Tensor, est: torch.Tensor, k: int, g: int, occupancy: f
     return x, r
 
 
-def estimate_learned(sk: Sketch, hosts, weights, stream=None, out=None):
-    """(learned estimates, closed-form estimates) at window k for all hosts."""
+def learned_workspace(sk: Sketch, n_hosts: int) -> torch.Tensor:
+    b = ctypes.c_size_t()
+    check(lib().vate_estimate_learned_workspace_bytes(sk.handle, n_hosts, ctypes.byref(b)), sk.handle)
+    ws = getattr(sk, "_lws", None)
+    if ws is None or ws.numel() < b.value:
+        ws = torch.empty(b.value, dtype=torch.uint8, device=sk.device)
+        sk._lws = ws
+    return ws
+
+
+def estimate_learned(sk: Sketch, hosts, weights, stream=None, out=None, partitioned=False):
+    """(learned estimates, closed-form estimates) at window k for all hosts.
+
+    partitioned=True uses vate_estimate_learned_ws (locality-ordered lookups)
+    with a workspace cached on the sketch."""
     ht = as_u32_tensor(hosts, sk.device)
     n = ht.numel()
     if out is None:
@@ -88,10 +103,14 @@ def estimate_learned(sk: Sketch, hosts, weights, stream=None, out=None):
         cf = torch.empty(n, dtype=torch.float32, device=sk.device)
     else:
         est, cf = out
-    check(lib().vate_estimate_learned(sk.handle, ht.data_ptr() if n else None, n,
-                                      weights.data_ptr(), est.data_ptr() if n else None,
-                                      cf.data_ptr() if n else None, _stream_handle(stream)),
-          sk.handle)
+    args = (sk.handle, ht.data_ptr() if n else None, n, weights.data_ptr(),
+            est.data_ptr() if n else None, cf.data_ptr() if n else None)
+    if partitioned and n:
+        ws = learned_workspace(sk, n)
+        check(lib().vate_estimate_learned_ws(*args, ws.data_ptr(), ws.numel(),
+                                             _stream_handle(stream)), sk.handle)
+    else:
+        check(lib().vate_estimate_learned(*args, _stream_handle(stream)), sk.handle)
     sk._keep_h = ht
     return est, cf
 

@@ -88,9 +88,25 @@ class Sketch:
     def close_slice(self, stream=None) -> None:
         check(lib().vate_close_slice(self._h, _stream_handle(stream)), self._h)
 
+    def workspace_bytes(self, n_hosts: int) -> int:
+        b = ctypes.c_size_t()
+        check(lib().vate_estimate_workspace_bytes(self._h, n_hosts, ctypes.byref(b)), self._h)
+        return b.value
+
+    def _workspace(self, n_hosts: int) -> torch.Tensor:
+        need = self.workspace_bytes(n_hosts)
+        ws = getattr(self, "_ws", None)
+        if ws is None or ws.numel() < need:
+            ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+            self._ws = ws
+        return ws
+
     def estimate(self, hosts, kprime: int | None = None, want_live: bool = True,
-                 want_hist: bool = False, stream=None, out=None):
-        """Returns (est float32, live int32 or None, hist int32 (n, k+1) or None)."""
+                 want_hist: bool = False, stream=None, out=None, partitioned: bool = False):
+        """Returns (est float32, live int32 or None, hist int32 (n, k+1) or None).
+
+        partitioned=True uses vate_estimate_ws (locality-ordered lookups) with a
+        workspace cached on the sketch; otherwise vate_estimate."""
         ht = as_u32_tensor(hosts, self.device)
         n = ht.numel()
         kp = self.cfg.k if kprime is None else kprime
@@ -101,13 +117,39 @@ class Sketch:
             live = torch.empty(n, dtype=torch.int32, device=self.device) if want_live else None
             hist = (torch.empty((n, self.cfg.k + 1), dtype=torch.int32, device=self.device)
                     if want_hist else None)
-        check(lib().vate_estimate(self._h, ht.data_ptr() if n else None, n, kp,
-                                  est.data_ptr() if n else None,
-                                  live.data_ptr() if (live is not None and n) else None,
-                                  hist.data_ptr() if (hist is not None and n) else None,
-                                  _stream_handle(stream)), self._h)
+        args = (self._h, ht.data_ptr() if n else None, n, kp,
+                est.data_ptr() if n else None,
+                live.data_ptr() if (live is not None and n) else None,
+                hist.data_ptr() if (hist is not None and n) else None)
+        if partitioned and n:
+            ws = self._workspace(n)
+            check(lib().vate_estimate_ws(*args, ws.data_ptr(), ws.numel(), _stream_handle(stream)),
+                  self._h)
+        else:
+            check(lib().vate_estimate(*args, _stream_handle(stream)), self._h)
         self._keep_h = ht
         return est, live, hist
+
+    def estimate_windows(self, hosts, kprimes, stream=None) -> torch.Tensor:
+        """Estimates for several windows (ascending k' values) from one pass:
+        float32 tensor [hosts][windows]."""
+        ht = as_u32_tensor(hosts, self.device)
+        n = ht.numel()
+        kp = np.ascontiguousarray(kprimes, dtype=np.uint32)
+        est = torch.empty((n, kp.size), dtype=torch.float32, device=self.device)
+        if n == 0:
+            return est
+        b = ctypes.c_size_t()
+        check(lib().vate_estimate_multi_workspace_bytes(self._h, n, ctypes.byref(b)), self._h)
+        ws = getattr(self, "_mws", None)
+        if ws is None or ws.numel() < b.value:
+            ws = torch.empty(b.value, dtype=torch.uint8, device=self.device)
+            self._mws = ws
+        check(lib().vate_estimate_multi_ws(self._h, ht.data_ptr(), n, kp.ctypes.data, kp.size,
+                                           est.data_ptr(), ws.data_ptr(), ws.numel(),
+                                           _stream_handle(stream)), self._h)
+        self._keep_h = ht
+        return est
 
     def census(self, stream=None) -> np.ndarray:
         out = np.zeros(self.cfg.k + 1, dtype=np.uint64)

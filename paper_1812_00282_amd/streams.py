@@ -137,3 +137,52 @@ def sweep_workload(k: int, width: int, log2_pool: int) -> Workload:
 
 
 SWEEP = [(2, 4, 26), (16, 8, 27), (64, 8, 28), (256, 16, 29)]
+
+
+# --------------------------------------------------------------------------
+# Batched sketches: 16 independent sketches with windows k in {8..128},
+# 8-bit ATs (16-bit for k = 128), pools 2^20..2^26, g = 1024, hosts per
+# sketch proportional to 2^(c-8), packets per sketch per slice
+# floor(10^U(5, 7)).
+# --------------------------------------------------------------------------
+
+@dataclass(frozen=True)
+class BatchMember:
+    log2_pool: int
+    width: int
+    k: int
+    g: int
+    n_hosts: int
+    seed: int
+
+
+def batch_members(seed: int = 4, n: int = 16, pool_range=(20, 26), g: int = 1024,
+                  host_shift: int = 8) -> list[BatchMember]:
+    rng = np.random.default_rng(np.random.SeedSequence([seed, 0xBA7C]))
+    out = []
+    for i in range(n):
+        k = int(rng.choice([8, 16, 32, 64, 128]))
+        c = int(rng.integers(pool_range[0], pool_range[1] + 1))
+        out.append(BatchMember(c, 16 if k == 128 else 8, k, g, 2 ** (c - host_shift),
+                               seed * 1000 + i))
+    return out
+
+
+def batch_packet_counts(seed: int, n_members: int, s: int, lo: float = 5.0, hi: float = 7.0) -> np.ndarray:
+    rng = np.random.default_rng(np.random.SeedSequence([seed, 0xC0C0, s]))
+    return np.floor(10.0 ** rng.uniform(lo, hi, size=n_members)).astype(np.int64)
+
+
+def member_slice_torch(m: BatchMember, hosts, s: int, n_packets: int, device):
+    """(n, 2) int32 pairs on the device: host uniform over the member's host
+    list, bip from a per-host universe of 256 (repeated contacts)."""
+    import torch
+
+    g = torch.Generator(device=device)
+    g.manual_seed(m.seed * 100003 + s)
+    h = torch.randint(0, hosts.numel(), (n_packets,), generator=g, device=device)
+    j = torch.randint(0, 256, (n_packets,), generator=g, device=device, dtype=torch.int64)
+    aip = hosts[h].to(torch.int64)
+    bip = (aip * 0x9E37 + j * 0x85EBCA6B + 0x1234567) % (2**32)
+    bip = bip - (bip >= 2**31).to(torch.int64) * 2**32
+    return torch.stack([hosts[h], bip.to(torch.int32)], 1).contiguous()

@@ -1,0 +1,155 @@
+"""Batched sketches (one persistent launch per phase, hipGraph replay,
+autotuned launch shapes): every member sketch bit-exact with the oracle and
+with the same sketch driven alone through the single-sketch calls."""
+import time
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle.vate_ref import OracleSketch  # noqa: E402
+from paper_1812_00282_amd import streams  # noqa: E402
+from paper_1812_00282_amd.batch import Batch  # noqa: E402
+from paper_1812_00282_amd.sketch import Config, Sketch  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+REL_TOL = 1e-6
+
+
+def _tol(ref_est, g):
+    return REL_TOL * np.abs(ref_est) + g * 64 * 2.0**-52
+
+
+def _u32(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+def _rand_slice(rng, hosts, n):
+    return np.stack([hosts[rng.integers(0, hosts.size, size=n)],
+                     rng.integers(0, 2**32, size=n, dtype=np.uint64).astype(np.uint32)], 1)
+
+
+SMALL = [Config(12, 8, 4, 64, 0, 1, 2), Config(10, 4, 3, 32, 0, 3, 4), Config(14, 8, 16, 128, 0, 5, 6),
+         Config(11, 16, 7, 64, 1, 7, 8), Config(12, 8, 1, 16, 0, 9, 10), Config(9, 4, 2, 16, 1, 11, 12),
+         Config(15, 16, 40, 256, 0, 13, 14)]
+
+
+def test_batch_matches_oracle():
+    rng = np.random.default_rng(0)
+    hosts = [rng.integers(0, 2**32, size=int(rng.integers(50, 600)), dtype=np.uint64).astype(np.uint32)
+             for _ in SMALL]
+    caps = [20000] * len(SMALL)
+    sks = [Sketch(c) for c in SMALL]
+    refs = [OracleSketch(c.log2_pool, c.width, c.k, c.g, c.seed_a, c.seed_b, c.partition) for c in SMALL]
+    b = Batch(sks, caps, hosts)
+    for t in range(30):
+        slices = [_rand_slice(rng, h, 0 if (t + i) % 9 == 8 else int(rng.integers(1, 20000)))
+                  for i, h in enumerate(hosts)]
+        b.load(slices)
+        b.slice()
+        for r, sl in zip(refs, slices):
+            r.ingest(sl)
+            r.close_slice()
+        if t % 3 == 2 or t == 29:
+            b.synchronize()
+            for i, (s, r) in enumerate(zip(sks, refs)):
+                pool, tt, bact0, closed = s.read_state()
+                assert (tt, bact0, closed) == (r.t, r.bact0, True), (t, i)
+                assert np.array_equal(pool, r.packed_pool()), (t, i)
+                assert np.array_equal(s.census(), r.census()), (t, i)
+                r_est, r_live, _ = r.estimate(hosts[i])
+                assert np.array_equal(_u32(b.live[i]), r_live), (t, i)
+                e = b.est[i].cpu().numpy().astype(np.float64)
+                assert np.all(np.abs(e - r_est) <= _tol(r_est, r.g)), (t, i)
+
+
+def _members_small():
+    ms = streams.batch_members(seed=4, pool_range=(14, 18), host_shift=6)
+    return ms
+
+
+def _run_pair(members, n_slices, counts_fn, graph=True, tune_at=None, check_every=1):
+    """Drive the members through a batch (eager first slice, then graph
+    replays) and the same configs through standalone sketches; compare."""
+    dev = torch.device("cuda")
+    cfgs = [Config(m.log2_pool, m.width, m.k, m.g, 0, m.seed, m.seed + 1) for m in members]
+    hosts = []
+    for m in members:
+        g = torch.Generator(device=dev)
+        g.manual_seed(m.seed)
+        hosts.append(torch.randint(-2**31, 2**31, (m.n_hosts,), generator=g, device=dev, dtype=torch.int64)
+                     .to(torch.int32))
+    counts = [counts_fn(s) for s in range(n_slices)]
+    caps = [int(max(c[i] for c in counts)) for i in range(len(members))]
+    A = [Sketch(c) for c in cfgs]
+    B = [Sketch(c) for c in cfgs]
+    batch = Batch(A, caps, hosts)
+    timing = {"eager": [], "replay": []}
+    report = None
+    for s in range(n_slices):
+        slices = [streams.member_slice_torch(m, hosts[i], s, int(counts[s][i]), dev)
+                  for i, m in enumerate(members)]
+        torch.cuda.synchronize()
+        batch.load(slices)
+        batch.synchronize()
+        t0 = time.perf_counter()
+        if s == 0 or not graph:
+            batch.slice()
+            kind = "eager"
+        else:
+            batch.replay()
+            kind = "replay"
+        batch.synchronize()
+        timing[kind].append(time.perf_counter() - t0)
+        if s == 0 and graph:
+            batch.capture()
+        if tune_at is not None and s == tune_at:
+            before = [e.clone() for e in batch.est]
+            report = batch.autotune()
+            batch.synchronize()
+            assert all(torch.equal(x, y) for x, y in zip(before, batch.est))
+            if graph:
+                batch.capture()
+        # eager torch work between replays
+        torch.randn(1 << 20, device=dev).sum().item()
+        refs = []
+        for i, sk in enumerate(B):
+            sk.ingest(slices[i])
+            sk.close_slice()
+            refs.append(sk.estimate(hosts[i]))
+        torch.cuda.synchronize()
+        if s % check_every == 0 or s == n_slices - 1:
+            for i in range(len(members)):
+                pa, ta, ba, ca = A[i].read_state()
+                pb, tb, bb, cb = B[i].read_state()
+                assert (ta, ba, ca) == (tb, bb, cb), (s, i)
+                assert np.array_equal(pa, pb), (s, i)
+                assert torch.equal(batch.est[i], refs[i][0]), (s, i)
+                assert torch.equal(batch.live[i], refs[i][1]), (s, i)
+    return timing, report
+
+
+def test_batch_graph_replay_equals_standalone():
+    members = _members_small()
+    counts = lambda s: streams.batch_packet_counts(4, len(members), s, lo=3.0, hi=5.0)
+    timing, _ = _run_pair(members, 12, counts, graph=True)
+    assert len(timing["replay"]) == 11
+
+
+def test_batch_autotune_keeps_results():
+    members = _members_small()[:8]
+    counts = lambda s: streams.batch_packet_counts(5, len(members), s, lo=3.0, hi=5.0)
+    _, report = _run_pair(members, 5, counts, graph=True, tune_at=1)
+    assert "best" in report and report["tune"]["estimate_block"] in (64, 128, 256)
+
+
+def test_batch_full_size_16_sketches():
+    """16 sketches, pools 2^20..2^26, 1e5..1e7 packets per sketch per slice,
+    g = 1024: eager first slice, autotune, captured graph replays; each member
+    bit-exact with its standalone twin at every slice."""
+    members = streams.batch_members(seed=4)
+    counts = lambda s: streams.batch_packet_counts(4, len(members), s)
+    timing, report = _run_pair(members, 5, counts, graph=True, tune_at=1)
+    print("batch timing (s)", timing, "tune", report["tune"] if report else None)

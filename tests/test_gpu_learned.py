@@ -140,9 +140,15 @@ def test_features_and_fused_learned_estimate():
     x, r = L.features(hist, est, wl.k, wl.g, occ)
     torch.cuda.synchronize()
     r_est, r_live, r_hist = ref.estimate(hosts, want_hist=True)
+    r_o = np.log(np.maximum(r_est, 1.0))
     xo = M.features(r_hist, r_hist[:, :wl.k].sum(1), wl.g, wl.k,
-                    (ref.N - ref.pool_inactive(wl.k)) / ref.N)
-    assert np.array_equal(x.cpu().numpy().view(np.uint16), _bf16_bits(xo))
+                    (ref.N - ref.pool_inactive(wl.k)) / ref.N, r_o)
+    xg = x.cpu().numpy().view(np.uint16)
+    xb = _bf16_bits(xo)
+    # histogram, live and occupancy columns exact; the log column within one
+    # BF16 step (FP32 logf vs FP64 log may round to neighbouring values)
+    assert np.array_equal(np.delete(xg, wl.k + 2, 1), np.delete(xb, wl.k + 2, 1))
+    assert np.all(np.abs(xg[:, wl.k + 2].astype(np.int32) - xb[:, wl.k + 2].astype(np.int32)) <= 1)
     np.testing.assert_allclose(r.cpu().numpy(), np.log(np.maximum(r_est, 1.0)), rtol=1e-6, atol=1e-6)
 
     p, _, _, _ = _problem(5, 1)
@@ -151,10 +157,12 @@ def test_features_and_fused_learned_estimate():
     w = L.pack(theta, L.new_weights())
     o = L.forward(w, x, r)
     e_learn, e_cf = L.estimate_learned(gpu, hosts, w)
+    p_learn, p_cf = L.estimate_learned(gpu, hosts, w, partitioned=True)
     torch.cuda.synchronize()
     assert torch.equal(e_cf, est)
+    assert torch.equal(p_cf, est) and torch.equal(p_learn, e_learn)
     np.testing.assert_allclose(e_learn.cpu().numpy(), np.exp(o.cpu().numpy().astype(np.float64)), rtol=1e-6)
-    ref_o, _ = M.forward(p, xo, np.log(np.maximum(r_est, 1.0)))
+    ref_o, _ = M.forward(p, xo, r_o)
     assert _rel_l2(e_learn.cpu().numpy(), np.exp(ref_o)) < 1e-3
 
 

@@ -48,18 +48,25 @@ def _check_state(gpu, ref, what=""):
 
 
 def _check_estimates(gpu, ref, hosts, kprime=None, hist=False, what=""):
-    est, live, hh = gpu.estimate(hosts, kprime=kprime, want_hist=hist)
-    torch.cuda.synchronize()
+    """Both estimate paths (direct gather and partitioned lookups) against
+    the oracle; the two paths must also agree bit for bit."""
     r_est, r_live, r_hist = ref.estimate(hosts, kprime=kprime, want_hist=hist)
-    assert np.array_equal(_u32(live), r_live), what
-    e = est.cpu().numpy().astype(np.float64)
-    err = np.abs(e - r_est)
-    ok = err <= _tol(r_est, ref.g)
-    assert ok.all(), f"{what}: {np.count_nonzero(~ok)} estimates off, worst rel " \
-                     f"{float(np.max(err / np.maximum(np.abs(r_est), 1e-300)))}"
-    if hist:
-        assert np.array_equal(_u32(hh), r_hist), what
-    return e, r_est
+    outs = []
+    for part in (False, True):
+        tag = f"{what} [{'partitioned' if part else 'direct'}]"
+        est, live, hh = gpu.estimate(hosts, kprime=kprime, want_hist=hist, partitioned=part)
+        torch.cuda.synchronize()
+        assert np.array_equal(_u32(live), r_live), tag
+        e = est.cpu().numpy().astype(np.float64)
+        err = np.abs(e - r_est)
+        ok = err <= _tol(r_est, ref.g)
+        assert ok.all(), f"{tag}: {np.count_nonzero(~ok)} estimates off, worst rel " \
+                         f"{float(np.max(err / np.maximum(np.abs(r_est), 1e-300)))}"
+        if hist:
+            assert np.array_equal(_u32(hh), r_hist), tag
+        outs.append(e)
+    assert np.array_equal(outs[0], outs[1]), what
+    return outs[0], r_est
 
 
 # ------------------------------------------------------------------ small --
@@ -338,10 +345,38 @@ def test_link40g_full_size_sampled():
     sample = pop.aips[np.random.default_rng(0).choice(pop.n_hosts, 10_000, replace=False)]
     _check_estimates(gpu, ref, sample, what="1% sample")
     est, live, _ = gpu.estimate(pop.aips)
+    est2, live2, _ = gpu.estimate(pop.aips, partitioned=True)
     cen = gpu.census()
     torch.cuda.synchronize()
+    assert torch.equal(est, est2) and torch.equal(live, live2)
     u_p = max(int(cen[wl.k]), 1)
     u_v = np.maximum(wl.g - _u32(live).astype(np.int64), 1)
     f64 = wl.g * (math.log(u_p / 2**wl.log2_pool)) - wl.g * np.log(u_v / wl.g)
     e = est.cpu().numpy().astype(np.float64)
     assert np.all(np.abs(e - f64) <= _tol(f64, wl.g))
+
+
+@pytest.mark.parametrize("w,k,c", [(8, 4, 16), (8, 60, 18), (16, 129, 18)])
+def test_multi_window_estimates(w, k, c):
+    """Estimates for many windows k' <= k from one pass equal the oracle's
+    single-window estimates for each k'."""
+    rng = np.random.default_rng(k)
+    cfg = Config(c, w, k, 128, seed_a=k, seed_b=c)
+    gpu, ref = _pair(cfg)
+    hosts = rng.integers(0, 2**32, size=700, dtype=np.uint64).astype(np.uint32)
+    for t in range(k + 6):
+        n = int(rng.integers(1, 5000))
+        pairs = np.stack([hosts[rng.integers(0, hosts.size, size=n)],
+                          rng.integers(0, 2**32, size=n, dtype=np.uint64).astype(np.uint32)], 1)
+        gpu.ingest(pairs)
+        ref.ingest(pairs)
+        gpu.close_slice()
+        ref.close_slice()
+    kps = sorted(set([1, 2, k // 2, k - 1, k] + list(rng.integers(1, k + 1, size=10))))
+    kps = [x for x in kps if 1 <= x <= k]
+    est = gpu.estimate_windows(hosts, kps)
+    torch.cuda.synchronize()
+    e = est.cpu().numpy().astype(np.float64)
+    for j, kp in enumerate(kps):
+        r_est, _, _ = ref.estimate(hosts, kprime=kp)
+        assert np.all(np.abs(e[:, j] - r_est) <= _tol(r_est, ref.g)), kp

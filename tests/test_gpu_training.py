@@ -1,0 +1,59 @@
+"""The learned estimator end to end: exact probe truth, training on states the
+plain method produces, and the committed network against the closed form on
+held-out streams (seeds 50-59)."""
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import brute  # noqa: E402
+from paper_1812_00282_amd import train as T  # noqa: E402
+from paper_1812_00282_amd.probes import ProbeEpisode  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def test_probe_truth_matches_hash_sets():
+    """Def. 1 by hash sets over the emitted pairs equals the probes' exact
+    window counts at every slice."""
+    k = 6
+    ep = ProbeEpisode(7, 40, 20, k, t_max=3000)
+    slices = []
+    for t in range(20):
+        pairs = ep.slice(t).cpu().numpy().view(np.uint32)
+        slices.append(pairs)
+        want = brute.window_truth(slices, t, k)
+        got = ep.truth(t).cpu().numpy()
+        aips = ep.aips_i32().cpu().numpy().view(np.uint32)
+        for a, n in zip(aips, got):
+            assert want.get(int(a), 0) == n, (t, a)
+
+
+@pytest.fixture(scope="module")
+def bg():
+    return T.background(4, torch.device("cuda"))
+
+
+def test_training_beats_closed_form_on_held_out(bg):
+    """A short training run (about 100k states, 3 epochs) already lowers the
+    mean relative error on held-out episodes below the closed form's."""
+    data = T.generate(range(2000, 2012), bg, n_slices=80, probes_range=(64, 256))
+    held = T.generate([50, 51], bg, n_slices=80, probes_range=(64, 256))
+    theta, hist = T.train(data, epochs=3, batch=2048, verbose=False)
+    res = T.evaluate(theta, held)
+    assert res["all"]["learned"] < res["all"]["closed_form"]
+    assert res["all"]["learned"] < res["all"]["closed_form_clamped"]
+
+
+def test_committed_network_beats_closed_form(bg):
+    """The committed network (trained by python -m paper_1812_00282_amd.train
+    on 10M states) against the closed form on the held-out seeds 50-59."""
+    assert os.path.exists(T.WEIGHTS), "trained weights are missing"
+    theta = T.load()
+    held = T.generate(T.HELD_OUT_SEEDS[:4], bg)
+    res = T.evaluate(theta, held)
+    print(res)
+    assert res["all"]["learned"] <= res["all"]["closed_form_clamped"]
+    assert res["all"]["learned"] <= res["all"]["closed_form"]

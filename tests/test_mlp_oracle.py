@@ -118,7 +118,7 @@ def test_adam_first_step_is_signed_lr():
 
 def test_features_layout():
     hist = np.array([[3, 1, 0, 124], [0, 0, 0, 128]], dtype=np.uint32)
-    x = M.features(hist, np.array([4, 0]), 128, 3, 0.25)
+    x = M.features(hist, np.array([4, 0]), 128, 3, 0.25, np.array([1.6, 0.0]))
     assert x.shape == (2, M.F)
-    assert np.allclose(x[0, :5], [3 / 128, 1 / 128, 0, 4 / 128, 0.25])
-    assert np.all(x[:, 5:] == 0)
+    assert np.allclose(x[0, :6], [3 / 128, 1 / 128, 0, 4 / 128, 0.25, 0.1])
+    assert np.all(x[:, 6:] == 0)
