@@ -110,6 +110,8 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=60)
     ap.add_argument("--warmup", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-eval", action="store_true",
+                    help="skip the learned vs closed-form comparison on held-out episodes")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device-to-device copy (reference kernel for "
                          "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE readings)")
@@ -222,10 +224,12 @@ def main() -> int:
                       "estimate": est_ms},
         "roofline": roofline,
     }
-    log("[bench] learned vs closed form on held-out probe episodes")
-    bg = T.background(4, dev)
-    held = T.generate(T.HELD_OUT_SEEDS[:2], bg, device=dev)
-    line["learned_vs_closed_form"] = {"weights": weights_src, **T.evaluate(theta, held, device=dev)}
+    if not args.no_eval:
+        log("[bench] learned vs closed form on held-out probe episodes")
+        bg = T.background(4, dev)
+        held = T.generate(T.HELD_OUT_SEEDS[:2], bg, device=dev)
+        line["learned_vs_closed_form"] = {"weights": weights_src,
+                                          **T.evaluate(theta, held, device=dev)}
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(wl, pop, host_slices)

@@ -64,7 +64,12 @@ typedef struct vate_params {
                             1: low-deviation blocks (Fig. 5) */
     uint32_t seed_a;     /* seed of H */
     uint32_t seed_b;     /* seed of BH */
-    uint32_t reserved;   /* must be 0 */
+    uint32_t counter;    /* 0: asynchronous timestamps (VATE, Sec. 3);
+                            1: distance recorders (VDRE, the baseline of Sec. 5:
+                            a DR holds the slices since its last hit, saturating
+                            at k, is reset to 0 by a packet and incremented for
+                            the whole pool at every slide, Sec. 1; it needs
+                            2^width >= k+1).  Same hashing, estimates and ABI. */
 } vate_params;
 
 typedef struct vate_sketch vate_sketch;

@@ -48,6 +48,8 @@
 
 typedef struct {
     uint32_t c, w, k, g, partition;
+    uint32_t counter;      /* 0: asynchronous timestamps (VATE); 1: distance
+                              recorders (VDRE, the paper's baseline) */
     uint32_t seed_a, seed_b;
     uint64_t N;            /* 2^c ATs in the pool ATP */
     uint16_t *ATP;         /* AT values in [0, 2k] */
@@ -162,13 +164,15 @@ uint32_t o_preserve_fast(uint32_t value, uint32_t act, uint32_t k)
 /* ---- sketch lifecycle ---- */
 
 o_vate *o_create(uint32_t c, uint32_t w, uint32_t k, uint32_t g,
-                 uint32_t seed_a, uint32_t seed_b, uint32_t partition)
+                 uint32_t seed_a, uint32_t seed_b, uint32_t partition, uint32_t counter)
 {
-    if (c < 1 || c > 32 || k < 1 || g < 1)
+    if (c < 1 || c > 32 || k < 1 || g < 1 || counter > 1)
         return NULL;
     if (w != 4 && w != 8 && w != 16)
         return NULL;
-    if ((1ull << w) < 2ull * k + 1)      /* ceil(log2(2k+1)) bits needed */
+    if (counter == 0 && (1ull << w) < 2ull * k + 1)   /* AT: ceil(log2(2k+1)) bits */
+        return NULL;
+    if (counter == 1 && (1ull << w) < 1ull * k + 1)   /* DR: ceil(log2(k+1)) bits */
         return NULL;
     if ((1ull << c) < 2ull * k)
         return NULL;
@@ -176,6 +180,7 @@ o_vate *o_create(uint32_t c, uint32_t w, uint32_t k, uint32_t g,
     if (!s)
         return NULL;
     s->c = c; s->w = w; s->k = k; s->g = g; s->partition = partition;
+    s->counter = counter;
     s->seed_a = seed_a; s->seed_b = seed_b;
     s->N = 1ull << c;
     s->ATP = (uint16_t *)malloc(s->N * sizeof(uint16_t));
@@ -184,9 +189,10 @@ o_vate *o_create(uint32_t c, uint32_t w, uint32_t k, uint32_t g,
         free(s->ATP); free(s->blk_start); free(s);
         return NULL;
     }
-    /* InitAT on every AT of ATP (Algorithm 4 init). */
+    /* InitAT on every AT of ATP (Algorithm 4 init): value 2k.  A DR starts
+     * as "not seen within k slices": value k. */
     for (uint64_t p = 0; p < s->N; p++)
-        s->ATP[p] = (uint16_t)(2 * k);
+        s->ATP[p] = (uint16_t)(counter == 0 ? 2 * k : k);
     /* Block ranges found by scanning block_of over the pool: block i starts
      * at the first pid mapped to it (empty blocks start where the next does). */
     for (uint64_t i = 0; i <= 2ull * k; i++)
@@ -217,6 +223,15 @@ static void o_advance(o_vate *s)
 {
     s->BACT0 = (s->BACT0 + 1) % (2 * s->k);
     s->t = s->t + 1;
+    if (s->counter == 1) {
+        /* DR (Sec. 1): every counter grows by one when the window slides;
+         * it saturates at k, which already means inactive for every k' <= k. */
+        for (uint64_t p = 0; p < s->N; p++)
+            if (s->ATP[p] < s->k)
+                s->ATP[p] = (uint16_t)(s->ATP[p] + 1);
+        s->closed = 0;
+        return;
+    }
     for (uint32_t i = 0; i < 2 * s->k; i++) {
         uint32_t bact = o_block_act(s, i);
         if (bact == 0 || bact == s->k) {
@@ -237,6 +252,10 @@ void o_ingest(o_vate *s, const uint32_t *pairs, uint64_t n)
         uint32_t aip = pairs[2 * j], bip = pairs[2 * j + 1];
         uint32_t vid = o_BH(s, bip);
         uint32_t pid = o_H(s, aip, vid);
+        if (s->counter == 1) {
+            s->ATP[pid] = 0;                      /* a DR is reset to 0 */
+            continue;
+        }
         uint32_t bid = o_block_of(s, pid);
         uint32_t act = (s->BACT0 + bid) % (2 * s->k);
         s->ATP[pid] = (uint16_t)act;              /* SetAT */
@@ -259,14 +278,33 @@ void o_close(o_vate *s)
     s->closed = 1;
 }
 
+/* DR check (Sec. 1): active in W(t-k'+1, k') iff its value is below k'. */
+int o_checkDR(uint32_t value, uint32_t kprime)
+{
+    return value < kprime;
+}
+
+/* CheckAT or the DR check of pool slot pid. */
+static int o_check(const o_vate *s, uint64_t pid, uint32_t kprime)
+{
+    if (s->counter == 1)
+        return o_checkDR(s->ATP[pid], kprime);
+    return o_checkAT(s->ATP[pid], o_act_of(s, pid), s->k, kprime);
+}
+
 /* Census of the pool at the end of the slice: hist[d] for d < k counts ATs
- * whose value is not 2k and whose distance is d; hist[k] counts the rest. */
+ * whose value is not 2k and whose distance is d; hist[k] counts the rest.
+ * For DR counters the distance is the value itself. */
 void o_census(const o_vate *s, uint64_t *hist)
 {
     for (uint32_t d = 0; d <= s->k; d++)
         hist[d] = 0;
     for (uint64_t p = 0; p < s->N; p++) {
         uint32_t v = s->ATP[p];
+        if (s->counter == 1) {
+            hist[v < s->k ? v : s->k]++;
+            continue;
+        }
         uint32_t act = o_act_of(s, p);
         if (v == 2 * s->k) {
             hist[s->k]++;
@@ -282,7 +320,7 @@ uint64_t o_pool_inactive(const o_vate *s, uint32_t kprime)
 {
     uint64_t u = 0;
     for (uint64_t p = 0; p < s->N; p++)
-        if (!o_checkAT(s->ATP[p], o_act_of(s, p), s->k, kprime))
+        if (!o_check(s, p, kprime))
             u++;
     return u;
 }
@@ -319,9 +357,13 @@ int o_estimate(const o_vate *s, const uint32_t *hosts, uint64_t nh,
         for (uint32_t i = 0; i < s->g; i++) {
             uint32_t pid = o_H(s, aip, i);             /* VAT_aip^i */
             uint32_t v = s->ATP[pid];
-            uint32_t act = o_act_of(s, pid);
-            if (!o_checkAT(v, act, s->k, kprime))
+            if (!o_check(s, pid, kprime))
                 u_v++;
+            if (hist && s->counter == 1) {
+                hist[h * (s->k + 1) + (v < s->k ? v : s->k)]++;
+                continue;
+            }
+            uint32_t act = o_act_of(s, pid);
             if (hist) {
                 uint32_t bin = s->k;
                 if (v != 2 * s->k) {

@@ -50,7 +50,8 @@ def lib():
             "o_checkAT": (_i32, [_u32, _u32, _u32, _u32]),
             "o_preserve_general": (_u32, [_u32, _u32, _u32]),
             "o_preserve_fast": (_u32, [_u32, _u32, _u32]),
-            "o_create": (_vp, [_u32, _u32, _u32, _u32, _u32, _u32, _u32]),
+            "o_create": (_vp, [_u32, _u32, _u32, _u32, _u32, _u32, _u32, _u32]),
+            "o_checkDR": (_i32, [_u32, _u32]),
             "o_destroy": (None, [_vp]),
             "o_ingest": (None, [_vp, _vp, _u64]),
             "o_close": (None, [_vp]),
@@ -112,11 +113,13 @@ class OracleSketch:
     """One VATE sketch on the CPU; same call sequence as the C-ABI library."""
 
     def __init__(self, log2_pool: int, width: int, k: int, g: int,
-                 seed_a: int = 0, seed_b: int = 0, partition: int = 0):
+                 seed_a: int = 0, seed_b: int = 0, partition: int = 0, counter: int = 0):
+        """counter 0: asynchronous timestamps (VATE); 1: distance recorders
+        (VDRE, full-pool maintenance every slice)."""
         self.c, self.w, self.k, self.g = log2_pool, width, k, g
-        self.partition = partition
+        self.partition, self.counter = partition, counter
         self._s = lib().o_create(log2_pool, width, k, g, seed_a & 0xFFFFFFFF,
-                                 seed_b & 0xFFFFFFFF, partition)
+                                 seed_b & 0xFFFFFFFF, partition, counter)
         if not self._s:
             raise ValueError("invalid oracle sketch parameters")
         self.N = lib().o_N(self._s)

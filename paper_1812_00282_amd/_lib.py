@@ -29,7 +29,7 @@ class VateParams(ctypes.Structure):
         ("partition", ctypes.c_uint32),
         ("seed_a", ctypes.c_uint32),
         ("seed_b", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32),
+        ("counter", ctypes.c_uint32),
     ]
 
 

@@ -68,11 +68,18 @@ static size_t state_bytes_for(uint32_t k, uint64_t N)
 int make_geo(const vate_params *p, Geo *G, const char **why)
 {
     if (!p) { *why = "params is NULL"; return VATE_E_INVAL; }
-    if (p->reserved != 0) { *why = "reserved must be 0"; return VATE_E_INVAL; }
+    if (p->counter > 1) { *why = "counter must be 0 (AT) or 1 (DR)"; return VATE_E_INVAL; }
     if (p->log2_pool < 1 || p->log2_pool > 32) { *why = "log2_pool must be in [1, 32]"; return VATE_E_INVAL; }
     if (p->width != 4 && p->width != 8 && p->width != 16) { *why = "width must be 4, 8 or 16"; return VATE_E_INVAL; }
     if (p->k < 1) { *why = "k must be >= 1"; return VATE_E_INVAL; }
-    if ((1ull << p->width) < 2ull * p->k + 1) { *why = "width too small: need 2^width >= 2k+1"; return VATE_E_INVAL; }
+    if (p->counter == 0 && (1ull << p->width) < 2ull * p->k + 1) {
+        *why = "width too small: an AT needs 2^width >= 2k+1";
+        return VATE_E_INVAL;
+    }
+    if (p->counter == 1 && (1ull << p->width) < 1ull * p->k + 1) {
+        *why = "width too small: a DR needs 2^width >= k+1";
+        return VATE_E_INVAL;
+    }
     if (p->g < 1 || p->g > 65535) { *why = "g must be in [1, 65535]"; return VATE_E_INVAL; }
     if (p->partition > 1) { *why = "partition must be 0 or 1"; return VATE_E_INVAL; }
     uint64_t N = 1ull << p->log2_pool;
@@ -88,6 +95,7 @@ int make_geo(const vate_params *p, Geo *G, const char **why)
     g.seed_a = p->seed_a;
     g.seed_b = p->seed_b;
     g.partition = p->partition;
+    g.dr = p->counter;
     const uint64_t E = 128 / p->width;   // ATs per 16-byte chunk
     if (p->partition == 0) {
         g.a = N / (g.twok - 1);
@@ -160,7 +168,7 @@ template <int W>
 __global__ void __launch_bounds__(256) k_init(Geo G, uint4 *__restrict__ pool4, uint64_t nchunks,
                                               DevState *__restrict__ st)
 {
-    const uint32_t pat = replicate<W>(G.twok);
+    const uint32_t pat = replicate<W>(inactive_value(G));
     const uint4 v = make_uint4(pat, pat, pat, pat);
     uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     for (; i < nchunks; i += (uint64_t)gridDim.x * blockDim.x) pool4[i] = v;
@@ -203,8 +211,9 @@ __device__ __forceinline__ void ingest_one(const Geo &G, uint8_t *__restrict__ p
 {
     uint32_t vid = bh(G, bip);
     uint32_t pid = vat_pid(G, host_key(G, aip), vid);
-    uint32_t act = block_act(G, bact0, block_of(G, pid));
-    set_at<W>(pool, pid, act);
+    // SetAT stores the block's ACT; a DR is reset to 0
+    uint32_t val = G.dr ? 0u : block_act(G, bact0, block_of(G, pid));
+    set_at<W>(pool, pid, val);
 }
 
 template <int W, bool ALIGNED16>
@@ -262,26 +271,32 @@ __device__ __forceinline__ uint32_t census_chunk(const Geo &G, const uint4 &v, u
                                                  uint32_t *hist, unsigned long long *census)
 {
     constexpr uint32_t E = 128 / W;
-    const uint32_t pat = replicate<W>(G.twok);
+    const uint32_t inact = inactive_value(G);
+    const uint32_t pat = replicate<W>(inact);
     if (v.x == pat && v.y == pat && v.z == pat && v.w == pat) return 0;
     uint32_t bits = 0;
     const uint64_t p0 = ch * E;
     uint32_t bid0 = 0, act0 = 0;
     uint64_t next = 0;
-    if (G.fast_blocks) {
+    if (G.fast_blocks && !G.dr) {
         bid0 = block_of(G, (uint32_t)p0);
         act0 = block_act(G, bact0, bid0);
         next = block_start(G, bid0 + 1);
     }
     for (uint32_t e = 0; e < E; ++e) {
         uint32_t val = chunk_get<W>(v, e);
-        if (val == G.twok) continue;
-        uint32_t act;
-        if (G.fast_blocks)
-            act = p0 + e < next ? act0 : block_act(G, bact0, bid0 + 1);
-        else
-            act = block_act(G, bact0, block_of(G, (uint32_t)(p0 + e)));
-        uint32_t d = at_dist(G, act, val);
+        if (val == inact) continue;
+        uint32_t d;
+        if (G.dr) {
+            d = val;                         // a DR holds its distance
+        } else {
+            uint32_t act;
+            if (G.fast_blocks)
+                act = p0 + e < next ? act0 : block_act(G, bact0, bid0 + 1);
+            else
+                act = block_act(G, bact0, block_of(G, (uint32_t)(p0 + e)));
+            d = at_dist(G, act, val);
+        }
         if (d < G.k) {
             bits |= 1u << e;
             if (hist) atomicAdd(&hist[d], 1u);
@@ -301,7 +316,7 @@ __global__ void __launch_bounds__(256) k_census(Geo G, const uint4 *__restrict__
         for (uint32_t d = threadIdx.x; d < G.k; d += blockDim.x) hist[d] = 0;
     __syncthreads();
     const uint32_t bact0 = st->bact0;
-    const uint32_t pat = replicate<W>(G.twok);
+    const uint32_t pat = replicate<W>(inactive_value(G));
     constexpr int U = 4;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t c0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c0 < nchunks; c0 += U * stride) {
@@ -399,9 +414,7 @@ __global__ void __launch_bounds__(256) k_estimate(Geo G, const uint8_t *__restri
                 ++live;
                 continue;
             }
-            const uint32_t val = load_at<W>(pool, pid[u]);
-            const uint32_t act = block_act(G, bact0, block_of(G, pid[u]));
-            const uint32_t d = at_dist(G, act, val);
+            const uint32_t d = value_dist(G, bact0, pid[u], load_at<W>(pool, pid[u]));
             live += d < kprime;
             if (HIST) {
                 ++live_k;
@@ -477,7 +490,7 @@ __global__ void __launch_bounds__(256) k_estimate_learned(Geo G, const uint8_t *
         for (int u = 0; u < kEstU; ++u) {
             if (!((byte[u] >> (pid[u] & 7u)) & 1u)) continue;
             const uint32_t val = load_at<W>(pool, pid[u]);
-            const uint32_t d = at_dist(G, block_act(G, bact0, block_of(G, pid[u])), val);
+            const uint32_t d = value_dist(G, bact0, pid[u], val);
             ++live;
             atomicAdd(&my[(d >> 1) * 65 + lane], 1u << ((d & 1u) << 4));
         }
@@ -635,7 +648,7 @@ __global__ void __launch_bounds__(kLookupThreads) k_part_lookup(Geo G, PartGeo P
                 continue;
             }
             const uint32_t pid = base_pid | local;
-            const uint32_t d = at_dist(G, block_act(G, bact0, block_of(G, pid)), load_at<W>(pool, pid));
+            const uint32_t d = value_dist(G, bact0, pid, load_at<W>(pool, pid));
             if (d < kprime) atomicAdd(&live[host], 1u);
             if (hist) atomicAdd(&hist[(size_t)host * (G.k + 1) + d], 1u);
         }
@@ -834,6 +847,37 @@ __global__ void __launch_bounds__(256) k_preserve(Geo G, uint4 *__restrict__ poo
     preserve_chunk<W>(G, pool4, st->bact0, (uint64_t)blockIdx.x * blockDim.x + threadIdx.x, max_chunks);
 }
 
+// ---------------------------------------------------------------------------
+// DR maintenance (the VDRE baseline of Sec. 5): at every slide each counter of
+// the pool grows by one, saturating at k (Sec. 1).  The whole pool is read;
+// a 16-byte chunk is written back only if one of its counters changed.
+// ---------------------------------------------------------------------------
+template <int W>
+__device__ __forceinline__ void dr_maintain_chunk(const Geo &G, uint4 *__restrict__ pool4, uint64_t ch)
+{
+    constexpr uint32_t E = 128 / W;
+    uint4 v = pool4[ch];
+    const uint32_t pat = replicate<W>(G.k);
+    if (v.x == pat && v.y == pat && v.z == pat && v.w == pat) return;
+    bool changed = false;
+    for (uint32_t e = 0; e < E; ++e) {
+        const uint32_t val = chunk_get<W>(v, e);
+        if (val < G.k) {
+            chunk_set<W>(v, e, val + 1);
+            changed = true;
+        }
+    }
+    if (changed) pool4[ch] = v;
+}
+
+template <int W>
+__global__ void __launch_bounds__(256) k_dr_maintain(Geo G, uint4 *__restrict__ pool4, uint64_t nchunks)
+{
+    for (uint64_t ch = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; ch < nchunks;
+         ch += (uint64_t)gridDim.x * blockDim.x)
+        dr_maintain_chunk<W>(G, pool4, ch);
+}
+
 #include "vate_batch_kernels.h"
 
 }  // namespace vate
@@ -933,9 +977,17 @@ static void dispatch_census(vate_sketch *s, hipStream_t st)
 static int advance(vate_sketch *s, hipStream_t st)
 {
     k_advance<<<1, 256, 0, st>>>(s->G, s->st);
-    if (s->p.width == 4) launch_preserve<4>(s, st);
-    else if (s->p.width == 8) launch_preserve<8>(s, st);
-    else launch_preserve<16>(s, st);
+    if (s->G.dr) {
+        const uint64_t nch = s->pool_bytes / 16;
+        const unsigned grid = grid_for(nch, 256, 8192);
+        if (s->p.width == 4) k_dr_maintain<4><<<grid, 256, 0, st>>>(s->G, reinterpret_cast<uint4 *>(s->pool), nch);
+        else if (s->p.width == 8) k_dr_maintain<8><<<grid, 256, 0, st>>>(s->G, reinterpret_cast<uint4 *>(s->pool), nch);
+        else k_dr_maintain<16><<<grid, 256, 0, st>>>(s->G, reinterpret_cast<uint4 *>(s->pool), nch);
+    } else {
+        if (s->p.width == 4) launch_preserve<4>(s, st);
+        else if (s->p.width == 8) launch_preserve<8>(s, st);
+        else launch_preserve<16>(s, st);
+    }
     s->closed = 0;
     return check_launch(s, "advance/preserve");
 }

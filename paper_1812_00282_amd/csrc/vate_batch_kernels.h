@@ -76,7 +76,8 @@ __global__ void k_batch_begin(BatchItem *__restrict__ items, uint32_t S, const u
         if ((adv_mask >> s) & 1ull) {
             it.st->bact0 = it.st->bact0 + 1 == it.G.twok ? 0 : it.st->bact0 + 1;
             it.st->t = it.st->t + 1;
-            tiles[PH_PRESERVE][s] = (2 * it.max_block_chunks + 255) / 256;
+            // AT: the two due blocks; DR: the whole pool
+            tiles[PH_PRESERVE][s] = it.G.dr ? (it.nchunks + 255) / 256 : (2 * it.max_block_chunks + 255) / 256;
         } else {
             tiles[PH_PRESERVE][s] = 0;
         }
@@ -122,6 +123,14 @@ __global__ void __launch_bounds__(256) k_batch_preserve(const BatchItem *__restr
         const uint64_t j = (tile - tab->prefix[PH_PRESERVE][s]) * 256 + threadIdx.x;
         uint4 *pool4 = reinterpret_cast<uint4 *>(it.pool);
         const uint32_t bact0 = it.st->bact0;
+        if (it.G.dr) {
+            if (j < it.nchunks) {
+                if (it.width == 4) dr_maintain_chunk<4>(it.G, pool4, j);
+                else if (it.width == 8) dr_maintain_chunk<8>(it.G, pool4, j);
+                else dr_maintain_chunk<16>(it.G, pool4, j);
+            }
+            continue;
+        }
         if (it.width == 4) preserve_chunk<4>(it.G, pool4, bact0, j, it.max_block_chunks);
         else if (it.width == 8) preserve_chunk<8>(it.G, pool4, bact0, j, it.max_block_chunks);
         else preserve_chunk<16>(it.G, pool4, bact0, j, it.max_block_chunks);
@@ -225,7 +234,7 @@ __device__ __forceinline__ uint32_t batch_host_live(const BatchItem &it, uint32_
                 ++live;
                 continue;
             }
-            const uint32_t d = at_dist(G, block_act(G, bact0, block_of(G, pid[u])), load_at<W>(it.pool, pid[u]));
+            const uint32_t d = value_dist(G, bact0, pid[u], load_at<W>(it.pool, pid[u]));
             live += d < it.kprime;
         }
     }

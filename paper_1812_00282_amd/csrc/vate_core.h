@@ -76,6 +76,7 @@ struct Geo {
     uint32_t k, twok, g;
     uint32_t seed_a, seed_b;
     uint32_t partition;  // 0: Eq. 9-10, 1: Fig. 5
+    uint32_t dr;         // 0: asynchronous timestamps; 1: distance recorders (VDRE)
     uint32_t base1;      // Fig. 5: index of the first (a'+1)-sized block, 2k - b'
     uint32_t fast_blocks;// every block but the last holds >= one 16-byte chunk
     Div32 div_a;         // divide by a (Eq. 9) or a' (Fig. 5)
@@ -138,6 +139,20 @@ __host__ __device__ __forceinline__ uint32_t at_dist(const Geo &G, uint32_t act,
 {
     int d = (int)act - (int)v;
     return (uint32_t)(d < 0 ? d + (int)G.twok : d);
+}
+
+// Value of a counter that is inactive for every window: 2k for an AT (Sec. 3),
+// k for a DR (a DR saturates at k, which already exceeds every k' - 1).
+__host__ __device__ __forceinline__ uint32_t inactive_value(const Geo &G)
+{
+    return G.dr ? G.k : G.twok;
+}
+
+// Distance of a stored value that is not inactive: Eq. 5 for an AT (from its
+// block's ACT); the value itself for a DR.
+__host__ __device__ __forceinline__ uint32_t value_dist(const Geo &G, uint32_t bact0, uint32_t pid, uint32_t v)
+{
+    return G.dr ? v : at_dist(G, block_act(G, bact0, block_of(G, pid)), v);
 }
 
 // Validate parameters and fill the geometry; returns VATE_OK or an error code

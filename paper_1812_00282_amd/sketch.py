@@ -39,10 +39,11 @@ class Config:
     partition: int = 0
     seed_a: int = 0
     seed_b: int = 0
+    counter: int = 0      # 0: asynchronous timestamps (VATE); 1: distance recorders (VDRE)
 
     def params(self) -> VateParams:
         return VateParams(self.log2_pool, self.width, self.k, self.g, self.partition,
-                          self.seed_a & 0xFFFFFFFF, self.seed_b & 0xFFFFFFFF, 0)
+                          self.seed_a & 0xFFFFFFFF, self.seed_b & 0xFFFFFFFF, self.counter)
 
 
 def state_bytes(cfg: Config) -> tuple[int, int]:

@@ -41,6 +41,7 @@ def test_library_exports_every_declared_symbol():
     dict(width=4, k=8), dict(width=8, k=128), dict(g=0), dict(g=65536),
     dict(partition=2), dict(log2_pool=3, k=3, width=4),   # 2^3 < 2k
     dict(log2_pool=4, width=4, k=1),                      # pool of 8 bytes < 16
+    dict(width=4, k=16, counter=1),                       # DR needs 2^w >= k+1
 ])
 def test_invalid_params_rejected(bad):
     base = dict(log2_pool=16, width=8, k=4, g=128)
@@ -51,11 +52,19 @@ def test_invalid_params_rejected(bad):
     assert e.value.code == _lib.VATE_E_INVAL
 
 
-def test_reserved_field_must_be_zero():
+def test_counter_kind_validated():
     p = Config(16, 8, 4, 128).params()
-    p.reserved = 1
+    p.counter = 2
     pb, sb = ctypes.c_size_t(), ctypes.c_size_t()
     assert _lib.lib().vate_state_bytes(ctypes.byref(p), ctypes.byref(pb), ctypes.byref(sb)) == _lib.VATE_E_INVAL
+
+
+def test_dr_width_rule():
+    """A DR needs ceil(log2(k+1)) bits (Sec. 1), one fewer than an AT: k = 8 fits
+    4-bit DRs but not 4-bit ATs."""
+    assert state_bytes(Config(16, 4, 8, 64, counter=1))[0] == (1 << 16) // 2
+    with pytest.raises(_lib.VateError):
+        state_bytes(Config(16, 4, 8, 64, counter=0))
 
 
 @pytest.mark.parametrize("c,w,k", [(16, 8, 4), (5, 4, 2), (28, 8, 60), (29, 16, 256), (32, 16, 300)])

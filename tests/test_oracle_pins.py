@@ -354,3 +354,53 @@ def test_packed_layout(w):
     bits = np.unpackbits(packed, bitorder="little").reshape(s.N, w)
     back = (bits.astype(np.uint32) << np.arange(w, dtype=np.uint32)).sum(1)
     assert np.array_equal(back, vals)
+
+
+# ---------------------------------------------------------- VDRE (DR) ----
+
+@pytest.mark.parametrize("k", [1, 2, 5, 9])
+def test_dr_state_matches_timestamps(k):
+    """DR counters (Sec. 1): reset to 0 on a hit, +1 per slide (saturating at
+    k); active for k' iff the value is below k' -- i.e. exactly the 64-bit
+    timestamp test for every slot, slice and k' <= k."""
+    rng = np.random.default_rng(100 + k)
+    c, g = 8, 16
+    s = OracleSketch(c, 8, k, g, seed_a=3, seed_b=4, counter=1)
+    ts = brute.TSPool(s.N)
+    hosts = rng.integers(0, 2**32, size=30, dtype=np.uint64).astype(np.uint32)
+    for t in range(4 * k + 8):
+        n = int(rng.integers(0, 200))
+        pairs = np.stack([hosts[rng.integers(0, 30, size=n)],
+                          rng.integers(0, 2**32, size=n, dtype=np.uint64).astype(np.uint32)], 1)
+        s.ingest(pairs)
+        ts.set(s.packet_pids(pairs), t)
+        s.close_slice()
+        vals = s.values().astype(np.int64)
+        assert np.array_equal(vals, np.minimum(ts.age(t), k))
+        for kp in range(1, k + 1):
+            assert s.pool_inactive(kp) == s.N - ts.active(t, kp).sum()
+
+
+@pytest.mark.parametrize("k,partition", [(3, 0), (9, 1), (16, 0)])
+def test_vate_equals_vdre(k, partition):
+    """The paper (Sec. 5): with the same hashing, VATE and VDRE give the same
+    estimates.  Live counts, histograms, census and estimates must be equal
+    at every slice for every window."""
+    rng = np.random.default_rng(k)
+    a = OracleSketch(10, 16, k, 64, seed_a=5, seed_b=6, partition=partition, counter=0)
+    d = OracleSketch(10, 16, k, 64, seed_a=5, seed_b=6, partition=partition, counter=1)
+    hosts = rng.integers(0, 2**32, size=40, dtype=np.uint64).astype(np.uint32)
+    for t in range(3 * k + 5):
+        n = int(rng.integers(0, 600))
+        pairs = np.stack([hosts[rng.integers(0, 40, size=n)],
+                          rng.integers(0, 2**32, size=n, dtype=np.uint64).astype(np.uint32)], 1)
+        a.ingest(pairs)
+        d.ingest(pairs)
+        a.close_slice()
+        d.close_slice()
+        assert np.array_equal(a.census(), d.census())
+        for kp in range(1, k + 1):
+            ea, la, ha = a.estimate(hosts, kprime=kp, want_hist=True)
+            ed, ld, hd = d.estimate(hosts, kprime=kp, want_hist=True)
+            assert np.array_equal(la, ld) and np.array_equal(ha, hd)
+            assert np.array_equal(ea, ed)
