@@ -7,9 +7,12 @@ both by the closed form (Eq. 11) and by the learned estimator (one pass over
 the VATs gives both).  Inputs (the packet stream and host list) are resident
 in HBM before the timed region starts.  After the timed region the learned
 and closed-form estimators are compared on held-out probe episodes with
-known cardinalities.  Prints one JSON line.
+known cardinalities, and 16 independent sketches of mixed geometry are run
+through the batched launches (graph replay against one-by-one calls).
+Prints one JSON line.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+                    [--no-eval] [--no-batch] [--copy-calibration]
 """
 from __future__ import annotations
 
@@ -104,6 +107,70 @@ def cpu_baseline(wl, pop, slices, budget_hosts: int = 20_000) -> dict:
     }
 
 
+def batched_leg(dev, n_slices: int = 8) -> dict:
+    """16 independent sketches (pools 2^20..2^26, k in {8..128}, g = 1024,
+    1e5..1e7 packets per sketch per slice) advanced a slice at a time by the
+    batched launches: the first slice eager, then the autotuner, a captured
+    graph and graph replays; the same sketches driven one after another
+    through the single-sketch calls give the comparison, and the last slice's
+    estimates of the two must be identical."""
+    import torch
+
+    from paper_1812_00282_amd import streams
+    from paper_1812_00282_amd.batch import Batch
+    from paper_1812_00282_amd.sketch import Config, Sketch
+
+    members = streams.batch_members(seed=4)
+    cfgs = [Config(m.log2_pool, m.width, m.k, m.g, 0, m.seed, m.seed + 1) for m in members]
+    hosts = []
+    for m in members:
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(m.seed)
+        hosts.append(torch.randint(-2**31, 2**31, (m.n_hosts,), generator=gen, device=dev,
+                                   dtype=torch.int64).to(torch.int32))
+    counts = [streams.batch_packet_counts(4, len(members), s) for s in range(n_slices)]
+    caps = [int(max(c[i] for c in counts)) for i in range(len(members))]
+    slices = [[streams.member_slice_torch(m, hosts[i], s, int(counts[s][i]), dev)
+               for i, m in enumerate(members)] for s in range(n_slices)]
+    batch = Batch([Sketch(c, device=dev) for c in cfgs], caps, hosts)
+    times, tune = [], None
+    for s in range(n_slices):
+        batch.load(slices[s])
+        batch.synchronize()
+        t0 = time.perf_counter()
+        if s == 0:
+            batch.slice()
+        else:
+            batch.replay()
+        batch.synchronize()
+        times.append(time.perf_counter() - t0)
+        if s == 0:
+            tune = batch.autotune()["tune"]
+            batch.capture()
+    solo = [Sketch(c, device=dev) for c in cfgs]
+    seq = []
+    for s in range(n_slices):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        outs = []
+        for i, sk in enumerate(solo):
+            sk.ingest(slices[s][i])
+            sk.close_slice()
+            outs.append(sk.estimate(hosts[i])[0])
+        torch.cuda.synchronize()
+        seq.append(time.perf_counter() - t0)
+    identical = all(torch.equal(batch.est[i], outs[i]) for i in range(len(members)))
+    replay_ms = float(np.median(times[2:])) * 1e3
+    seq_ms = float(np.median(seq[2:])) * 1e3
+    pkts = float(np.mean([c.sum() for c in counts[2:]]))
+    hosts_n = sum(m.n_hosts for m in members)
+    return {"sketches": len(members), "packets_per_slice": pkts, "hosts_per_slice": hosts_n,
+            "eager_first_slice_ms": times[0] * 1e3, "graph_replay_ms": replay_ms,
+            "one_by_one_ms": seq_ms, "packets_per_s": pkts / (replay_ms * 1e-3),
+            "speedup_vs_one_by_one": seq_ms / replay_ms, "identical_to_one_by_one": identical,
+            "tune": tune}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -112,6 +179,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-eval", action="store_true",
                     help="skip the learned vs closed-form comparison on held-out episodes")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batched-sketches leg (16 sketches, hipGraph replay)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device-to-device copy (reference kernel for "
                          "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE readings)")
@@ -198,7 +267,7 @@ def main() -> int:
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                 "traffic_source": traffic_src,
-                "kernel": "estimate phase: k_part_scatter + k_part_lookup<8> + k_part_finalize_learned",
+                "kernel": "estimate phase: k_run_scatter + k_run_lookup<8> + k_run_finalize + k_learned_rows",
                 "algorithmic_bytes_per_launch": bytes_per_host * pop.n_hosts,
                 "avg_launch_ms": est_ms,
                 "random_lines_per_s": wl.g * pop.n_hosts / (est_ms * 1e-3)}
@@ -230,6 +299,11 @@ def main() -> int:
         held = T.generate(T.HELD_OUT_SEEDS[:2], bg, device=dev)
         line["learned_vs_closed_form"] = {"weights": weights_src,
                                           **T.evaluate(theta, held, device=dev)}
+    if not args.no_batch:
+        log("[bench] batched sketches")
+        del sk
+        torch.cuda.empty_cache()
+        line["batched"] = batched_leg(dev)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(wl, pop, host_slices)

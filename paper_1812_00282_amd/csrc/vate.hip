@@ -538,242 +538,7 @@ __global__ void __launch_bounds__(256) k_estimate_learned(Geo G, const uint8_t *
     }
 }
 
-// ---------------------------------------------------------------------------
-// Partitioned estimate.  The direct gather above touches one random cache
-// line per VAT anywhere in the bitmap, so every VAT costs a line fill from
-// beyond L2.  Here the same CheckAT lookups are reordered for locality:
-//
-//  k_part_scatter: a workgroup hashes the g VATs of its 256 hosts twice:
-//    first counting them per pool slice (2^20 ATs, i.e. a 128 KiB bitmap
-//    slice), then writing one 32-bit entry (host within the workgroup, AT
-//    within the slice) per VAT into the workgroup's own region of the
-//    workspace, grouped by slice.  Regions are fixed (256 g entries), so no
-//    global scan or atomics are needed; per-slice counts and offsets of each
-//    region are stored beside it.
-//  k_part_lookup: a workgroup owns one slice: it loads the slice of the
-//    activity bitmap into LDS and streams the entries of that slice from all
-//    regions, resolving each with an LDS read.  Only the rare active VATs go
-//    further (AT value for the distance when needed, atomic add into the
-//    host's live count and histogram).
-//  k_part_finalize: per host, Eq. 11 from the counts.
-//
-// HBM traffic per host is about 8 g bytes of streamed entries (written once,
-// read once) instead of g random line fills.
-// ---------------------------------------------------------------------------
-constexpr uint32_t kSliceLog2 = 20;                 // ATs per slice = 2^20
-constexpr uint32_t kPartHosts = 256;                // hosts per scatter workgroup
-constexpr uint32_t kLookupThreads = 1024;
-constexpr uint32_t kMaxSlices = 4096;               // 2^32 / 2^20
-
-struct PartGeo {
-    uint32_t slice_log2;     // min(c, 20)
-    uint32_t n_slices;       // N >> slice_log2
-    uint32_t n_groups;       // ceil(n_hosts / 256)
-    uint32_t reps;           // lookup workgroups per slice
-    uint64_t region;         // entries per group region = 256 g
-};
-
-__global__ void __launch_bounds__(kPartHosts) k_part_scatter(Geo G, PartGeo PG,
-                                                            const uint32_t *__restrict__ hosts, uint32_t n,
-                                                            uint32_t *__restrict__ entries,
-                                                            uint32_t *__restrict__ cnt_out,
-                                                            uint32_t *__restrict__ off_out)
-{
-    __shared__ uint32_t cnt[kMaxSlices];
-    __shared__ uint32_t cur[kMaxSlices];
-    const uint32_t ns = PG.n_slices, sl = PG.slice_log2;
-    for (uint32_t b = threadIdx.x; b < ns; b += blockDim.x) cnt[b] = 0;
-    __syncthreads();
-    const uint32_t h = blockIdx.x * kPartHosts + threadIdx.x;
-    const bool valid = h < n;
-    const uint32_t key = host_key(G, valid ? hosts[h] : 0u);
-    if (valid)
-        for (uint32_t i = 0; i < G.g; ++i) atomicAdd(&cnt[vat_pid(G, key, i) >> sl], 1u);
-    __syncthreads();
-    // exclusive prefix over slices (one thread; ns <= 4096 and this runs once per group)
-    if (threadIdx.x == 0) {
-        uint32_t run = 0;
-        for (uint32_t b = 0; b < ns; ++b) {
-            cur[b] = run;
-            run += cnt[b];
-        }
-    }
-    __syncthreads();
-    for (uint32_t b = threadIdx.x; b < ns; b += blockDim.x) {
-        cnt_out[(size_t)blockIdx.x * ns + b] = cnt[b];
-        off_out[(size_t)blockIdx.x * ns + b] = cur[b];
-    }
-    __syncthreads();
-    uint32_t *region = entries + (size_t)blockIdx.x * PG.region;
-    const uint32_t mask = (1u << sl) - 1u;
-    if (valid)
-        for (uint32_t i = 0; i < G.g; ++i) {
-            const uint32_t pid = vat_pid(G, key, i);
-            const uint32_t slot = atomicAdd(&cur[pid >> sl], 1u);
-            region[slot] = (threadIdx.x << sl) | (pid & mask);
-        }
-}
-
-template <int W>
-__global__ void __launch_bounds__(kLookupThreads) k_part_lookup(Geo G, PartGeo PG, const uint8_t *__restrict__ pool,
-                                                               const DevState *__restrict__ st,
-                                                               const uint8_t *__restrict__ bitmap,
-                                                               const uint32_t *__restrict__ entries,
-                                                               const uint32_t *__restrict__ cnt_in,
-                                                               const uint32_t *__restrict__ off_in,
-                                                               uint32_t n, uint32_t kprime,
-                                                               uint32_t *__restrict__ live,
-                                                               uint32_t *__restrict__ hist)
-{
-    extern __shared__ uint32_t bits[];     // the slice's bitmap, 2^slice_log2 bits
-    const uint32_t b = blockIdx.x / PG.reps, rep = blockIdx.x % PG.reps;
-    const uint32_t sl = PG.slice_log2, mask = (1u << sl) - 1u;
-    const uint32_t words = ((1u << sl) + 31) / 32;
-    const uint32_t *src = reinterpret_cast<const uint32_t *>(bitmap) + (size_t)b * words;
-    for (uint32_t i = threadIdx.x; i < words; i += blockDim.x) bits[i] = src[i];
-    __syncthreads();
-    const uint32_t bact0 = st->bact0;
-    const bool need_dist = hist != nullptr || kprime < G.k;
-    const uint32_t base_pid = b << sl;
-    for (uint32_t grp = rep; grp < PG.n_groups; grp += PG.reps) {
-        const uint32_t cnt = cnt_in[(size_t)grp * PG.n_slices + b];
-        const uint32_t *e = entries + (size_t)grp * PG.region + off_in[(size_t)grp * PG.n_slices + b];
-        for (uint32_t j = threadIdx.x; j < cnt; j += blockDim.x) {
-            const uint32_t ent = e[j];
-            const uint32_t local = ent & mask;
-            if (!((bits[local >> 5] >> (local & 31u)) & 1u)) continue;
-            const uint32_t host = grp * kPartHosts + (ent >> sl);
-            if (!need_dist) {
-                atomicAdd(&live[host], 1u);
-                continue;
-            }
-            const uint32_t pid = base_pid | local;
-            const uint32_t d = value_dist(G, bact0, pid, load_at<W>(pool, pid));
-            if (d < kprime) atomicAdd(&live[host], 1u);
-            if (hist) atomicAdd(&hist[(size_t)host * (G.k + 1) + d], 1u);
-        }
-    }
-    (void)n;
-}
-
-__global__ void k_part_finalize(Geo G, const DevState *__restrict__ st, uint32_t n, uint32_t kprime,
-                                const uint32_t *__restrict__ live, float *__restrict__ est,
-                                uint32_t *__restrict__ live_out, uint32_t *__restrict__ hist)
-{
-    const uint64_t active_pool = pool_active(st, kprime);
-    const uint32_t h = blockIdx.x * blockDim.x + threadIdx.x;
-    if (h >= n) return;
-    const uint32_t lv = live[h];
-    est[h] = estimate_from_counts(G.g - lv, G.N - active_pool, G.g, G.c);
-    if (live_out) live_out[h] = lv;
-    if (hist) {
-        uint32_t *row = hist + (size_t)h * (G.k + 1);
-        uint32_t s = 0;
-        for (uint32_t d = 0; d < G.k; ++d) s += row[d];
-        row[G.k] = G.g - s;
-    }
-}
-
-// Learned estimate after the partitioned lookups (window k): per wavefront 16
-// hosts' features are built from their histogram rows, run through the
-// network on the matrix cores, and both estimates are written.
-__global__ void __launch_bounds__(256) k_part_finalize_learned(Geo G, const DevState *__restrict__ st, uint32_t n,
-                                                               const uint32_t *__restrict__ live,
-                                                               const uint32_t *__restrict__ hist,
-                                                               const mlp::Packed *__restrict__ P,
-                                                               float *__restrict__ est, float *__restrict__ cf_out)
-{
-    __shared__ __attribute__((aligned(16))) uint16_t xs_all[4][16 * mlp::LDS_STRIDE];
-    __shared__ __attribute__((aligned(16))) uint16_t a1_all[4][16 * mlp::LDS_STRIDE];
-    __shared__ float cf_all[4][16];
-    const uint64_t active_pool = pool_active(st, G.k);
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63, q = l >> 4, c = l & 15;
-    const uint32_t h0 = blockIdx.x * 64 + 16 * w;
-    const float fg = (float)G.g, occupancy = (float)active_pool / (float)G.N;
-    if (l < 16) {
-        const uint32_t h = h0 + l;
-        const float cf = h < n ? estimate_from_counts(G.g - live[h], G.N - active_pool, G.g, G.c) : 0.f;
-        cf_all[w][l] = cf;
-        if (h < n) cf_out[h] = cf;
-    }
-    __syncthreads();
-    uint16_t *xs = xs_all[w];
-    for (int e = l; e < 16 * VATE_MLP_FEATURES; e += 64) {
-        const int m = e >> 6, f = e & 63;
-        const uint32_t h = h0 + m;
-        float x = 0.f;
-        if (h < n) {
-            if (f < (int)G.k)
-                x = (float)hist[(size_t)h * (G.k + 1) + f] / fg;
-            else if (f == (int)G.k)
-                x = (float)live[h] / fg;
-            else if (f == (int)G.k + 1)
-                x = occupancy;
-            else if (f == (int)G.k + 2)
-                x = logf(fmaxf(cf_all[w][m], 1.0f)) * 0.0625f;
-        }
-        xs[m * mlp::LDS_STRIDE + f] = mlp::bf16_bits(x);
-    }
-    __syncthreads();
-    float r4[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) r4[r] = logf(fmaxf(cf_all[w][4 * q + r], 1.0f));
-    mlp::f32x4 z1[4], z2[4];
-    float a2v[4][4], o4[4];
-    mlp::forward16(P, xs, a1_all[w], r4, z1, z2, a2v, o4);
-    if (c < 4) {
-        const uint32_t h = h0 + 4 * q + c;
-        if (h < n) {
-            const float ex = expf(o4[c]);
-            est[h] = isfinite(ex) ? ex : cf_all[w][4 * q + c];
-        }
-    }
-}
-
-// Several windows from one pass: the pool's active count for every window
-// (prefix of the census), then per host the prefix of its distance histogram
-// gives live(k') for each requested k' (ascending), and Eq. 11 for each.
-constexpr uint32_t kMaxWindows = 64;
-
-struct Windows {
-    uint32_t m;
-    uint32_t kp[kMaxWindows];
-};
-
-__global__ void k_census_prefix(Geo G, const DevState *__restrict__ st, unsigned long long *__restrict__ cum)
-{
-    if (threadIdx.x == 0) {
-        unsigned long long run = 0;
-        cum[0] = 0;
-        for (uint32_t d = 0; d < G.k; ++d) {
-            run += census_of(st)[d];
-            cum[d + 1] = run;
-        }
-    }
-}
-
-__global__ void k_part_finalize_multi(Geo G, uint32_t n, Windows win, const unsigned long long *__restrict__ cum,
-                                      const uint32_t *__restrict__ hist, float *__restrict__ est)
-{
-    const uint32_t h = blockIdx.x * blockDim.x + threadIdx.x;
-    if (h >= n) return;
-    const uint32_t *row = hist + (size_t)h * (G.k + 1);
-    uint32_t live = 0, j = 0;
-    for (uint32_t d = 0; d < G.k && j < win.m; ++d) {
-        live += row[d];
-        while (j < win.m && win.kp[j] == d + 1) {
-            est[(size_t)h * win.m + j] = estimate_from_counts(G.g - live, G.N - cum[d + 1], G.g, G.c);
-            ++j;
-        }
-    }
-}
-
-__global__ void k_fill_u32(uint32_t *__restrict__ p, uint64_t count)
-{
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
-         i += (uint64_t)gridDim.x * blockDim.x)
-        p[i] = 0u;
-}
+#include "vate_part.h"
 
 // ---------------------------------------------------------------------------
 // Slice advance: BACT^0 = (BACT^0 + 1) mod 2k, t = t + 1 (Alg. 4 end of loop),
@@ -1017,74 +782,137 @@ static void launch_estimate_learned(vate_sketch *s, const uint32_t *hosts, uint3
         s->G, s->pool, s->st, s->bitmap, hosts, n, static_cast<const mlp::Packed *>(weights), est, cf);
 }
 
-// ---- partitioned estimate: workspace layout and launches ----
-static PartGeo part_geo(const vate_sketch *s, uint64_t n)
+// ---- partitioned estimate: geometry, workspace layout and launches ----
+// part_geo returns false when the sketch or host count is outside the
+// partitioned path's limits (a pool above 1 GiB, or g VATs of one host too
+// many for one LDS sort); the entry points then use the direct gather.
+static bool part_geo(const vate_sketch *s, uint64_t n, PartGeo *out)
 {
-    PartGeo pg;
-    pg.slice_log2 = s->G.c < kSliceLog2 ? s->G.c : kSliceLog2;
-    pg.n_slices = (uint32_t)(s->G.N >> pg.slice_log2);
-    pg.n_groups = (uint32_t)((n + kPartHosts - 1) / kPartHosts);
-    pg.region = (uint64_t)kPartHosts * s->G.g;
-    // enough lookup workgroups to cover every CU about twice
-    uint32_t reps = (512 + pg.n_slices - 1) / pg.n_slices;
-    if (reps > pg.n_groups) reps = pg.n_groups;
-    pg.reps = reps < 1 ? 1 : reps;
-    return pg;
+    const Geo &G = s->G;
+    const uint32_t w = s->p.width;
+    const uint32_t wlog = w == 4 ? 2u : (w == 8 ? 3u : 4u);
+    uint32_t sl = kSliceBytesLog2 + 3u - wlog;          // 2^sl ATs of w bits = 128 KiB
+    if (sl > G.c) sl = G.c;
+    const uint64_t ns = G.N >> sl;
+    if (ns > kRunMaxSlices) return false;
+    PartGeo p{};
+    p.sl = sl;
+    p.n_slices = (uint32_t)ns;
+    p.sub = p.n_slices < kSuper ? p.n_slices : kSuper;
+    p.n_super = p.n_slices / p.sub;
+    p.xcd = p.n_super >= 8 ? 1u : 0u;
+    p.rowp = (G.k + 2u) / 2u;
+    p.dbytes = G.k < 255 ? 1u : 2u;
+    const uint64_t nsp = (ns + 3) & ~3ull;
+    int sh = (int)kRunMaxHostsLog2;
+    for (; sh >= 0; --sh) {
+        const uint64_t hosts = 1ull << sh, vats = hosts * G.g;
+        const uint64_t lds = 4 * (nsp + ((hosts + 3) & ~3ull) + vats);
+        if (vats <= kRunMaxEntries && lds <= kRunLdsBudget && hosts * p.rowp * 4 <= kFinHistBytes) break;
+    }
+    if (sh < 0) return false;
+    p.sh = (uint32_t)sh;
+    p.n_sub = (uint32_t)((n + (1ull << sh) - 1) >> sh);
+    p.vats = (1u << sh) * G.g;
+    p.region = (p.vats + 63u) & ~63u;
+    p.dq = kRunThreads / G.g;
+    p.dr = kRunThreads % G.g;
+    p.fast = G.a >= (1ull << sl) ? 1u : 0u;
+    p.lds_scatter = (uint32_t)(4 * (nsp + (((1ull << sh) + 3) & ~3ull) + p.vats));
+    p.lds_lookup = (uint32_t)(((((uint64_t)w << sl) >> 3) + 15) & ~15ull);
+    p.lds_final = (1u << sh) * p.rowp * 4u;
+    *out = p;
+    return true;
 }
-
-struct PartWs {
-    uint32_t *entries, *cnt, *off, *live;
-    size_t bytes;
-};
 
 static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
-static PartWs part_ws(const PartGeo &pg, uint64_t n, void *base)
+struct RunWs {
+    uint32_t *entries;          // [n_sub][region] sorted entries
+    void *dist;                 // [n_sub][region] distances (u8 or u16)
+    uint16_t *table;            // [n_super + 1][n_sub][sub] run starts
+    unsigned long long *cum;    // [k + 1] census prefix (several windows)
+    uint32_t *rows;             // [n_sub 2^sh][rowp] packed histograms (learned estimate)
+    size_t bytes;
+};
+
+static RunWs run_ws(const PartGeo &pg, uint32_t k, void *base, bool learned = false)
 {
-    PartWs w;
-    uint8_t *p = static_cast<uint8_t *>(base);
+    RunWs w;
+    const uintptr_t p = reinterpret_cast<uintptr_t>(base);
+    const size_t ents = (size_t)pg.n_sub * pg.region;
     size_t off = 0;
     w.entries = reinterpret_cast<uint32_t *>(p + off);
-    off += align256((size_t)pg.n_groups * pg.region * 4);
-    w.cnt = reinterpret_cast<uint32_t *>(p + off);
-    off += align256((size_t)pg.n_groups * pg.n_slices * 4);
-    w.off = reinterpret_cast<uint32_t *>(p + off);
-    off += align256((size_t)pg.n_groups * pg.n_slices * 4);
-    w.live = reinterpret_cast<uint32_t *>(p + off);
-    off += align256((size_t)n * 4);
+    off += align256(ents * 4);
+    w.dist = reinterpret_cast<void *>(p + off);
+    off += align256(ents * pg.dbytes);
+    w.table = reinterpret_cast<uint16_t *>(p + off);
+    off += align256((size_t)(pg.n_super + 1) * pg.n_sub * pg.sub * 2);
+    w.cum = reinterpret_cast<unsigned long long *>(p + off);
+    off += align256((size_t)(k + 1) * 8);
+    w.rows = reinterpret_cast<uint32_t *>(p + off);
+    if (learned) off += align256(((size_t)pg.n_sub << pg.sh) * pg.rowp * 4);
     w.bytes = off;
     return w;
 }
 
-template <int W>
-static int launch_estimate_part(vate_sketch *s, const uint32_t *hosts, uint32_t n, uint32_t kprime, float *est,
-                                uint32_t *live, uint32_t *hist, void *ws, hipStream_t st,
-                                const void *weights = nullptr, float *cf = nullptr)
+static int set_lds_limit(vate_sketch *s, const void *fn, uint32_t bytes)
 {
-    const PartGeo pg = part_geo(s, n);
-    const PartWs w = part_ws(pg, n, ws);
-    if (weights) hist = reinterpret_cast<uint32_t *>(static_cast<uint8_t *>(ws) + w.bytes);
-    const uint32_t words = ((1u << pg.slice_log2) + 31) / 32;
-    const size_t lds = (size_t)words * 4;
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_part_lookup<W>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)(4u << kSliceLog2 >> 5));
-        if (e != hipSuccess) return fail(s, VATE_E_DEVICE, hipGetErrorString(e));
-        attr_set = true;
-    }
-    k_fill_u32<<<grid_for(n, 256, 4096), 256, 0, st>>>(w.live, n);
-    if (hist) k_fill_u32<<<grid_for((uint64_t)n * (s->G.k + 1), 256, 8192), 256, 0, st>>>(hist, (uint64_t)n * (s->G.k + 1));
-    k_part_scatter<<<pg.n_groups, kPartHosts, 0, st>>>(s->G, pg, hosts, n, w.entries, w.cnt, w.off);
-    k_part_lookup<W><<<pg.n_slices * pg.reps, kLookupThreads, lds, st>>>(s->G, pg, s->pool, s->st, s->bitmap,
-                                                                        w.entries, w.cnt, w.off, n, kprime,
-                                                                        w.live, hist);
-    if (weights)
-        k_part_finalize_learned<<<grid_for(n, 64, 1u << 30), 256, 0, st>>>(
-            s->G, s->st, n, w.live, hist, static_cast<const mlp::Packed *>(weights), est, cf);
-    else
-        k_part_finalize<<<grid_for(n, 256, 1u << 30), 256, 0, st>>>(s->G, s->st, n, kprime, w.live, est, live, hist);
+    const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return fail(s, VATE_E_DEVICE, hipGetErrorString(e));
     return VATE_OK;
+}
+
+template <int W, typename DT, int MODE>
+static int launch_part_typed(vate_sketch *s, const PartGeo &pg, const RunWs &w, const uint32_t *hosts, uint32_t n,
+                             uint32_t kprime, float *est, uint32_t *live, uint32_t *hist, const Windows &win,
+                             const void *weights, float *cf, hipStream_t st)
+{
+    static bool attr = false;
+    if (!attr) {
+        int rc = set_lds_limit(s, reinterpret_cast<const void *>(&k_run_scatter), kRunLdsBudget);
+        if (rc == VATE_OK)
+            rc = set_lds_limit(s, reinterpret_cast<const void *>(&k_run_lookup<W, DT>), 1u << kSliceBytesLog2);
+        if (rc == VATE_OK)
+            rc = set_lds_limit(s, reinterpret_cast<const void *>(&k_run_finalize<DT, MODE>), kFinHistBytes);
+        if (rc != VATE_OK) return rc;
+        attr = true;
+    }
+    DT *dist = static_cast<DT *>(w.dist);
+    k_run_scatter<<<pg.n_sub, kRunThreads, pg.lds_scatter, st>>>(s->G, pg, hosts, n, w.entries, w.table);
+    k_run_lookup<W, DT><<<pg.n_slices, kRunThreads, pg.lds_lookup, st>>>(s->G, pg, s->pool, s->st, w.entries,
+                                                                          w.table, dist);
+    if (MODE == kFinMulti) k_census_prefix<<<1, 64, 0, st>>>(s->G, s->st, w.cum);
+    k_run_finalize<DT, MODE><<<pg.n_sub, kFinThreads, pg.lds_final, st>>>(
+        s->G, pg, s->st, n, kprime, w.entries, dist, est, live, MODE == kFinLearned ? w.rows : hist, win, w.cum,
+        static_cast<const mlp::Packed *>(weights), cf);
+    if (MODE == kFinLearned)
+        k_learned_rows<<<(n + 63) / 64, 256, 0, st>>>(s->G, s->st, n, pg.rowp, w.rows, cf,
+                                                       static_cast<const mlp::Packed *>(weights), est);
+    return VATE_OK;
+}
+
+template <int W, int MODE>
+static int launch_part(vate_sketch *s, const PartGeo &pg, void *ws, const uint32_t *hosts, uint32_t n,
+                       uint32_t kprime, float *est, uint32_t *live, uint32_t *hist, const Windows &win,
+                       const void *weights, float *cf, hipStream_t st)
+{
+    const RunWs w = run_ws(pg, s->p.k, ws, MODE == kFinLearned);
+    if (pg.dbytes == 1)
+        return launch_part_typed<W, uint8_t, MODE>(s, pg, w, hosts, n, kprime, est, live, hist, win, weights, cf, st);
+    return launch_part_typed<W, uint16_t, MODE>(s, pg, w, hosts, n, kprime, est, live, hist, win, weights, cf, st);
+}
+
+template <int MODE>
+static int launch_part_w(vate_sketch *s, const PartGeo &pg, void *ws, const uint32_t *hosts, uint32_t n,
+                         uint32_t kprime, float *est, uint32_t *live, uint32_t *hist, const Windows &win,
+                         const void *weights, float *cf, hipStream_t st)
+{
+    if (s->p.width == 4)
+        return launch_part<4, MODE>(s, pg, ws, hosts, n, kprime, est, live, hist, win, weights, cf, st);
+    if (s->p.width == 8)
+        return launch_part<8, MODE>(s, pg, ws, hosts, n, kprime, est, live, hist, win, weights, cf, st);
+    return launch_part<16, MODE>(s, pg, ws, hosts, n, kprime, est, live, hist, win, weights, cf, st);
 }
 
 extern "C" {
@@ -1200,8 +1028,8 @@ int vate_estimate_workspace_bytes(const vate_sketch *s, size_t n_hosts, size_t *
 {
     if (!s || !bytes) return VATE_E_INVAL;
     if (n_hosts > 0xFFFFFFFFull - 1024) return VATE_E_INVAL;
-    const PartGeo pg = part_geo(s, n_hosts);
-    *bytes = part_ws(pg, n_hosts, nullptr).bytes;
+    PartGeo pg;
+    *bytes = part_geo(s, n_hosts, &pg) ? run_ws(pg, s->p.k, nullptr).bytes : 256;
     return VATE_OK;
 }
 
@@ -1225,10 +1053,17 @@ int vate_estimate_ws(vate_sketch *s, const uint32_t *hosts_dev, size_t n_hosts, 
         return fail(s, VATE_E_INVAL, "hosts/est/live/hist must be non-NULL (live, hist may be NULL) and 4-byte aligned");
     hipStream_t st = static_cast<hipStream_t>(stream);
     const uint32_t n = (uint32_t)n_hosts;
-    int rc;
-    if (s->p.width == 4) rc = launch_estimate_part<4>(s, hosts_dev, n, kprime, est_dev, live_dev, hist_dev, workspace_dev, st);
-    else if (s->p.width == 8) rc = launch_estimate_part<8>(s, hosts_dev, n, kprime, est_dev, live_dev, hist_dev, workspace_dev, st);
-    else rc = launch_estimate_part<16>(s, hosts_dev, n, kprime, est_dev, live_dev, hist_dev, workspace_dev, st);
+    PartGeo pg;
+    if (!part_geo(s, n, &pg)) {      // outside the partitioned limits: direct gather
+        if (hist_dev && s->p.k > (uint32_t)kMaxHistK)
+            return fail(s, VATE_E_UNSUPPORTED, "per-host histogram of this geometry needs k <= 256");
+        if (s->p.width == 4) launch_estimate<4>(s, hosts_dev, n, kprime, est_dev, live_dev, hist_dev, st);
+        else if (s->p.width == 8) launch_estimate<8>(s, hosts_dev, n, kprime, est_dev, live_dev, hist_dev, st);
+        else launch_estimate<16>(s, hosts_dev, n, kprime, est_dev, live_dev, hist_dev, st);
+        return check_launch(s, "estimate_ws");
+    }
+    const int rc = launch_part_w<kFinClosedForm>(s, pg, workspace_dev, hosts_dev, n, kprime, est_dev, live_dev,
+                                                 hist_dev, Windows{}, nullptr, nullptr, st);
     if (rc != VATE_OK) return rc;
     return check_launch(s, "estimate_ws");
 }
@@ -1253,11 +1088,15 @@ int vate_estimate_learned_ws(vate_sketch *s, const uint32_t *hosts_dev, size_t n
         return fail(s, VATE_E_INVAL, "hosts/est/est_cf must be 4-byte and weights 256-byte aligned, non-NULL");
     hipStream_t st = static_cast<hipStream_t>(stream);
     const uint32_t n = (uint32_t)n_hosts;
-    const uint32_t k = s->p.k;
-    int rc;
-    if (s->p.width == 4) rc = launch_estimate_part<4>(s, hosts_dev, n, k, est_dev, nullptr, nullptr, workspace_dev, st, weights_dev, est_cf_dev);
-    else if (s->p.width == 8) rc = launch_estimate_part<8>(s, hosts_dev, n, k, est_dev, nullptr, nullptr, workspace_dev, st, weights_dev, est_cf_dev);
-    else rc = launch_estimate_part<16>(s, hosts_dev, n, k, est_dev, nullptr, nullptr, workspace_dev, st, weights_dev, est_cf_dev);
+    PartGeo pg;
+    if (!part_geo(s, n, &pg)) {      // outside the partitioned limits: fused direct gather
+        if (s->p.width == 4) launch_estimate_learned<4>(s, hosts_dev, n, weights_dev, est_dev, est_cf_dev, st);
+        else if (s->p.width == 8) launch_estimate_learned<8>(s, hosts_dev, n, weights_dev, est_dev, est_cf_dev, st);
+        else launch_estimate_learned<16>(s, hosts_dev, n, weights_dev, est_dev, est_cf_dev, st);
+        return check_launch(s, "estimate_learned_ws");
+    }
+    const int rc = launch_part_w<kFinLearned>(s, pg, workspace_dev, hosts_dev, n, s->p.k, est_dev, nullptr, nullptr,
+                                              Windows{}, weights_dev, est_cf_dev, st);
     if (rc != VATE_OK) return rc;
     return check_launch(s, "estimate_learned_ws");
 }
@@ -1266,9 +1105,11 @@ int vate_estimate_multi_workspace_bytes(const vate_sketch *s, size_t n_hosts, si
 {
     if (!s || !bytes) return VATE_E_INVAL;
     if (n_hosts > 0xFFFFFFFFull - 1024) return VATE_E_INVAL;
-    const PartGeo pg = part_geo(s, n_hosts);
-    *bytes = part_ws(pg, n_hosts, nullptr).bytes + align256((size_t)n_hosts * (s->p.k + 1) * 4) +
-             align256(8ull * (s->p.k + 1));
+    PartGeo pg;
+    if (part_geo(s, n_hosts, &pg))
+        *bytes = run_ws(pg, s->p.k, nullptr).bytes;
+    else    // direct gather into full histograms, then the windows
+        *bytes = align256((size_t)n_hosts * (s->p.k + 1) * 4) + align256(8ull * (s->p.k + 1));
     return VATE_OK;
 }
 
@@ -1297,20 +1138,24 @@ int vate_estimate_multi_ws(vate_sketch *s, const uint32_t *hosts_dev, size_t n_h
         return fail(s, VATE_E_INVAL, "hosts/est must be non-NULL and 4-byte aligned");
     hipStream_t st = static_cast<hipStream_t>(stream);
     const uint32_t n = (uint32_t)n_hosts;
-    const PartGeo pg = part_geo(s, n);
-    const size_t base = part_ws(pg, n, nullptr).bytes;
+    PartGeo pg;
+    if (part_geo(s, n, &pg)) {
+        const int rc = launch_part_w<kFinMulti>(s, pg, workspace_dev, hosts_dev, n, s->p.k, est_dev, nullptr,
+                                                nullptr, win, nullptr, nullptr, st);
+        if (rc != VATE_OK) return rc;
+        return check_launch(s, "estimate_multi_ws");
+    }
+    if (s->p.k > (uint32_t)kMaxHistK)
+        return fail(s, VATE_E_UNSUPPORTED, "several windows for this geometry need k <= 256");
     uint8_t *ws = static_cast<uint8_t *>(workspace_dev);
-    uint32_t *hist = reinterpret_cast<uint32_t *>(ws + base);
-    unsigned long long *cum =
-        reinterpret_cast<unsigned long long *>(ws + base + align256((size_t)n * (s->p.k + 1) * 4));
-    int rc;
-    // the lookups for window k fill the per-host histograms (est is scratch here)
-    if (s->p.width == 4) rc = launch_estimate_part<4>(s, hosts_dev, n, s->p.k, est_dev, nullptr, hist, ws, st);
-    else if (s->p.width == 8) rc = launch_estimate_part<8>(s, hosts_dev, n, s->p.k, est_dev, nullptr, hist, ws, st);
-    else rc = launch_estimate_part<16>(s, hosts_dev, n, s->p.k, est_dev, nullptr, hist, ws, st);
-    if (rc != VATE_OK) return rc;
+    uint32_t *hist = reinterpret_cast<uint32_t *>(ws);
+    unsigned long long *cum = reinterpret_cast<unsigned long long *>(ws + align256((size_t)n * (s->p.k + 1) * 4));
+    // the direct gather for window k fills the per-host histograms (est is scratch here)
+    if (s->p.width == 4) launch_estimate<4>(s, hosts_dev, n, s->p.k, est_dev, nullptr, hist, st);
+    else if (s->p.width == 8) launch_estimate<8>(s, hosts_dev, n, s->p.k, est_dev, nullptr, hist, st);
+    else launch_estimate<16>(s, hosts_dev, n, s->p.k, est_dev, nullptr, hist, st);
     k_census_prefix<<<1, 64, 0, st>>>(s->G, s->st, cum);
-    k_part_finalize_multi<<<grid_for(n, 256, 1u << 30), 256, 0, st>>>(s->G, n, win, cum, hist, est_dev);
+    k_multi_from_hist<<<grid_for(n, 256, 1u << 30), 256, 0, st>>>(s->G, n, win, cum, hist, est_dev);
     return check_launch(s, "estimate_multi_ws");
 }
 
@@ -1318,8 +1163,8 @@ int vate_estimate_learned_workspace_bytes(const vate_sketch *s, size_t n_hosts, 
 {
     if (!s || !bytes) return VATE_E_INVAL;
     if (n_hosts > 0xFFFFFFFFull - 1024) return VATE_E_INVAL;
-    const PartGeo pg = part_geo(s, n_hosts);
-    *bytes = part_ws(pg, n_hosts, nullptr).bytes + align256((size_t)n_hosts * (s->p.k + 1) * 4);
+    PartGeo pg;
+    *bytes = part_geo(s, n_hosts, &pg) ? run_ws(pg, s->p.k, nullptr, true).bytes : 256;
     return VATE_OK;
 }
 

@@ -1,0 +1,522 @@
+// Partitioned estimate: the g CheckAT lookups of every host (Alg. 4's
+// estimate loop, Alg. 1) routed to the pool slice that holds their AT,
+// resolved out of LDS, and routed back.  Included into vate.hip inside
+// namespace vate.
+//
+// The direct gather reads one random cache line per VAT anywhere in the
+// pool, so it is bound by line fills from beyond L2.  Here:
+//
+//  k_run_scatter  one workgroup per subgroup of 2^sh hosts.  Hashes the
+//                 subgroup's VATs once (pids stay in registers), counts them
+//                 per pool slice in LDS, places them by an LDS counting sort
+//                 and copies the sorted entries (host within subgroup, AT
+//                 within slice) to the workspace as one coalesced stream.
+//                 The start of every (subgroup, slice) run goes to a u16
+//                 table laid out [super-slice][subgroup][slice in super].
+//  k_run_lookup   one workgroup per pool slice (128 KiB of ATs, held in LDS).
+//                 Walks that slice's run in every subgroup and writes each
+//                 VAT's distance (Eq. 5, CheckAT; k = inactive for window k)
+//                 beside its entry.  The 8 slices of a super-slice are given
+//                 to one XCD: their runs are adjacent in memory, so the lines
+//                 they read and the distance bytes they write meet in that
+//                 XCD's L2.
+//  k_run_finalize one workgroup per subgroup.  Streams the entries and
+//                 distances back, builds each host's distance histogram in LDS
+//                 and forms Eq. 11 for k', several windows, or the learned
+//                 estimate from it.
+//
+// HBM traffic per VAT: 4 B entry written and read back twice, 1 B (2 B when
+// k >= 255) distance written and read once.
+
+constexpr uint32_t kRunThreads = 1024;                          // scatter / lookup workgroup
+constexpr uint32_t kRunPerThread = 32;                          // VATs hashed per scatter thread
+constexpr uint32_t kRunMaxEntries = kRunThreads * kRunPerThread; // VATs per subgroup
+constexpr uint32_t kRunLdsBudget = 152u * 1024u;                // scatter LDS ceiling (bytes)
+constexpr uint32_t kSliceBytesLog2 = 17;                        // pool bytes per slice: 128 KiB
+constexpr uint32_t kRunMaxSlices = 8192;                        // pools up to 1 GiB
+constexpr uint32_t kRunMaxHostsLog2 = 10;                       // hosts per subgroup <= 1024
+constexpr uint32_t kSuper = 8;                                  // slices per super-slice
+constexpr uint32_t kFinThreads = 256;
+constexpr uint32_t kFinHistBytes = 64u * 1024u;                 // per-subgroup histogram ceiling
+
+struct PartGeo {
+    uint32_t sl;          // ATs per slice = 2^sl
+    uint32_t n_slices;    // N >> sl
+    uint32_t sub;         // slices per super-slice, min(8, n_slices)
+    uint32_t n_super;     // n_slices / sub
+    uint32_t sh;          // hosts per subgroup = 2^sh
+    uint32_t n_sub;       // subgroups
+    uint32_t vats;        // 2^sh * g
+    uint32_t region;      // entries between subgroup regions (vats rounded up to 64)
+    uint32_t dq, dr;      // kRunThreads = dq * g + dr
+    uint32_t fast;        // every block holds >= 2^sl ATs: a slice meets at most two blocks
+    uint32_t rowp;        // u32 words per packed 16-bit histogram row, ceil((k + 1) / 2)
+    uint32_t xcd;         // map the slices of a super-slice to one XCD
+    uint32_t lds_scatter, lds_lookup, lds_final;
+    uint32_t dbytes;      // bytes per stored distance: 1 if k < 255, else 2
+};
+
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kRunThreads) k_run_scatter(Geo G, PartGeo PG, const uint32_t *__restrict__ hosts,
+                                                            uint32_t n, uint32_t *__restrict__ entries,
+                                                            uint16_t *__restrict__ table)
+{
+    extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
+    __shared__ uint32_t wsum[kRunThreads / 64];
+    const uint32_t nsp = (PG.n_slices + 3u) & ~3u;
+    const uint32_t nkp = ((1u << PG.sh) + 3u) & ~3u;
+    uint32_t *cnt = lds;                  // [n_slices] counts, then cursors
+    uint32_t *keys = lds + nsp;           // [2^sh] host keys
+    uint32_t *sorted = keys + nkp;        // [vats] entries sorted by slice
+    const uint32_t s = blockIdx.x, t = threadIdx.x;
+    const uint32_t h0 = s << PG.sh;
+    const uint32_t nh = min(1u << PG.sh, n - h0);
+    const uint32_t nv = nh * G.g;
+    for (uint32_t b = t; b < PG.n_slices; b += kRunThreads) cnt[b] = 0;
+    for (uint32_t h = t; h < nh; h += kRunThreads) keys[h] = host_key(G, hosts[h0 + h]);
+    __syncthreads();
+
+    // VAT v = t + j * kRunThreads is VAT i = v mod g of host v / g.
+    const uint32_t sl = PG.sl, mask = (1u << sl) - 1u;
+    const uint32_t host_t = t / G.g, i_t = t - host_t * G.g;
+    uint32_t pid[kRunPerThread];
+    {
+        uint32_t host = host_t, i = i_t;
+#pragma unroll
+        for (uint32_t j = 0; j < kRunPerThread; ++j) {
+            if (t + j * kRunThreads < nv) {
+                pid[j] = vat_pid(G, keys[host], i);
+                atomicAdd(&cnt[pid[j] >> sl], 1u);
+            }
+            i += PG.dr;
+            host += PG.dq;
+            if (i >= G.g) {
+                i -= G.g;
+                ++host;
+            }
+        }
+    }
+    __syncthreads();
+
+    // Exclusive scan of the slice counts; thread t owns counters [t per, (t+1) per).
+    const uint32_t per = (PG.n_slices + kRunThreads - 1) / kRunThreads;
+    const uint32_t b0 = t * per;
+    uint32_t mine = 0;
+    for (uint32_t q = 0; q < per; ++q)
+        if (b0 + q < PG.n_slices) mine += cnt[b0 + q];
+    const uint32_t lane = t & 63u, wv = t >> 6;
+    uint32_t incl = mine;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(incl, off, 64);
+        if (lane >= (uint32_t)off) incl += y;
+    }
+    if (lane == 63) wsum[wv] = incl;
+    __syncthreads();
+    uint32_t run = incl - mine;
+    for (uint32_t q = 0; q < wv; ++q) run += wsum[q];
+    for (uint32_t q = 0; q < per; ++q) {
+        const uint32_t b = b0 + q;
+        if (b >= PG.n_slices) break;
+        const uint32_t c = cnt[b];
+        cnt[b] = run;
+        const uint32_t B = b / PG.sub, jj = b - B * PG.sub;
+        table[((size_t)B * PG.n_sub + s) * PG.sub + jj] = (uint16_t)run;
+        run += c;
+    }
+    if (t == 0) table[((size_t)PG.n_super * PG.n_sub + s) * PG.sub] = (uint16_t)nv;
+    __syncthreads();
+
+    {
+        uint32_t host = host_t, i = i_t;
+#pragma unroll
+        for (uint32_t j = 0; j < kRunPerThread; ++j) {
+            if (t + j * kRunThreads < nv) {
+                const uint32_t slot = atomicAdd(&cnt[pid[j] >> sl], 1u);
+                sorted[slot] = (host << sl) | (pid[j] & mask);
+            }
+            i += PG.dr;
+            host += PG.dq;
+            if (i >= G.g) {
+                i -= G.g;
+                ++host;
+            }
+        }
+    }
+    __syncthreads();
+    uint32_t *out = entries + (size_t)s * PG.region;
+    const uint32_t n4 = nv >> 2;
+    for (uint32_t q = t; q < n4; q += kRunThreads)
+        reinterpret_cast<uint4 *>(out)[q] = reinterpret_cast<const uint4 *>(sorted)[q];
+    for (uint32_t q = (n4 << 2) + t; q < nv; q += kRunThreads) out[q] = sorted[q];
+}
+
+// ---------------------------------------------------------------------------
+template <typename DT>
+__device__ __forceinline__ void store4(DT *p, const uint32_t d[4])
+{
+    if constexpr (sizeof(DT) == 1)
+        *reinterpret_cast<uint32_t *>(p) = d[0] | (d[1] << 8) | (d[2] << 16) | (d[3] << 24);
+    else
+        *reinterpret_cast<uint2 *>(p) = make_uint2(d[0] | (d[1] << 16), d[2] | (d[3] << 16));
+}
+
+template <typename DT>
+__device__ __forceinline__ void load4(const DT *p, uint32_t d[4])
+{
+    if constexpr (sizeof(DT) == 1) {
+        const uint32_t v = *reinterpret_cast<const uint32_t *>(p);
+        d[0] = v & 0xFFu, d[1] = (v >> 8) & 0xFFu, d[2] = (v >> 16) & 0xFFu, d[3] = v >> 24;
+    } else {
+        const uint2 v = *reinterpret_cast<const uint2 *>(p);
+        d[0] = v.x & 0xFFFFu, d[1] = v.x >> 16, d[2] = v.y & 0xFFFFu, d[3] = v.y >> 16;
+    }
+}
+
+template <int W, typename DT>
+__global__ void __launch_bounds__(kRunThreads) k_run_lookup(Geo G, PartGeo PG, const uint8_t *__restrict__ pool,
+                                                           const DevState *__restrict__ st,
+                                                           const uint32_t *__restrict__ entries,
+                                                           const uint16_t *__restrict__ table, DT *__restrict__ dist)
+{
+    extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
+    const uint8_t *at = reinterpret_cast<const uint8_t *>(lds);
+    uint32_t B, j;
+    if (PG.xcd) {              // workgroup x runs on XCD x mod 8
+        const uint32_t r = blockIdx.x & 7u, rest = blockIdx.x >> 3;
+        j = rest % PG.sub;
+        B = (rest / PG.sub) * 8u + r;
+    } else {
+        B = blockIdx.x / PG.sub;
+        j = blockIdx.x % PG.sub;
+    }
+    const uint32_t b = B * PG.sub + j;
+    const uint32_t sl = PG.sl, mask = (1u << sl) - 1u;
+    const uint32_t nbytes = (uint32_t)(((uint64_t)W << sl) >> 3);
+    const uint8_t *src = pool + (uint64_t)b * nbytes;
+    if ((nbytes & 15u) == 0) {
+        for (uint32_t q = threadIdx.x; q < nbytes / 16; q += kRunThreads)
+            reinterpret_cast<uint4 *>(lds)[q] = reinterpret_cast<const uint4 *>(src)[q];
+    } else {
+        for (uint32_t q = threadIdx.x; q < nbytes; q += kRunThreads)
+            reinterpret_cast<uint8_t *>(lds)[q] = src[q];
+    }
+    __syncthreads();
+
+    const uint32_t bact0 = st->bact0;
+    const uint32_t inact = inactive_value(G);
+    const uint32_t first = b << sl;
+    uint32_t act0 = 0, act1 = 0, split = 0;
+    if (PG.fast) {             // the slice meets block bid0 and at most block bid0 + 1
+        const uint32_t bid0 = block_of(G, first);
+        act0 = block_act(G, bact0, bid0);
+        const uint64_t nxt = block_start(G, bid0 + 1);
+        split = nxt - first > (uint64_t)mask ? mask + 1u : (uint32_t)(nxt - first);
+        act1 = block_act(G, bact0, bid0 + 1 < G.twok ? bid0 + 1 : bid0);
+    }
+    auto dist_of = [&](uint32_t local) -> uint32_t {
+        const uint32_t v = load_at<W>(at, local);
+        if (v == inact) return G.k;
+        uint32_t d;
+        if (G.dr) {
+            d = v;
+        } else {
+            const uint32_t act = PG.fast ? (local < split ? act0 : act1)
+                                         : block_act(G, bact0, block_of(G, first | local));
+            d = at_dist(G, act, v);
+        }
+        return d < G.k ? d : G.k;
+    };
+
+    // Eight lanes per subgroup run, four entries (one 16-byte chunk) per lane.
+    // A wavefront takes 64 subgroups at a time: one coalesced read of their
+    // run bounds, then the first chunk of eight runs per lane group is loaded
+    // before any is used (eight independent loads in flight per lane); the
+    // rare chunks beyond a run's first eight follow in a second pass.
+    const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+    const uint32_t grp = lane >> 3, gl = lane & 7u;
+    const size_t row = (size_t)B * PG.n_sub, next_row = (size_t)(B + 1) * PG.n_sub;
+    auto resolve = [&](uint32_t s, uint32_t c, uint32_t start, uint32_t end, const uint4 &e4) {
+        DT *dst = dist + (size_t)s * PG.region;
+        const uint32_t e[4] = {e4.x, e4.y, e4.z, e4.w};
+        uint32_t d[4];
+        bool full = true;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const uint32_t idx = 4u * c + m;
+            const bool valid = idx >= start && idx < end;
+            full = full && valid;
+            d[m] = valid ? dist_of(e[m] & mask) : 0u;
+        }
+        if (full) {
+            store4<DT>(dst + 4u * c, d);
+        } else {
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const uint32_t idx = 4u * c + m;
+                if (idx >= start && idx < end) dst[idx] = (DT)d[m];
+            }
+        }
+    };
+    // Software pipeline over groups of 64 subgroups: while group i is
+    // resolved, the entries of group i + 1 and the run bounds of group i + 2
+    // are already in flight.
+    auto bounds = [&](uint32_t s0, uint32_t &st_l, uint32_t &en_l) {
+        st_l = en_l = 0;
+        if (s0 + lane < PG.n_sub) {
+            const size_t cell = (row + s0 + lane) * PG.sub;
+            st_l = table[cell + j];
+            en_l = j + 1 < PG.sub ? table[cell + j + 1] : table[(next_row + s0 + lane) * PG.sub];
+        }
+    };
+    auto issue = [&](uint32_t s0, uint32_t st_l, uint32_t en_l, uint4 e4[8]) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const uint32_t start = __shfl(st_l, 8 * q + (int)grp, 64), end = __shfl(en_l, 8 * q + (int)grp, 64);
+            const uint32_t c = (start >> 2) + gl;
+            e4[q] = make_uint4(0u, 0u, 0u, 0u);
+            if (c < ((end + 3u) >> 2))
+                e4[q] = reinterpret_cast<const uint4 *>(entries + (size_t)(s0 + 8 * q + grp) * PG.region)[c];
+        }
+    };
+    auto finish = [&](uint32_t s0, uint32_t st_l, uint32_t en_l, const uint4 e4[8]) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const uint32_t start = __shfl(st_l, 8 * q + (int)grp, 64), end = __shfl(en_l, 8 * q + (int)grp, 64);
+            const uint32_t c = (start >> 2) + gl;
+            if (c < ((end + 3u) >> 2)) resolve(s0 + 8 * q + grp, c, start, end, e4[q]);
+        }
+        for (int q = 0; q < 8; ++q) {      // chunks beyond a run's first eight
+            const uint32_t start = __shfl(st_l, 8 * q + (int)grp, 64), end = __shfl(en_l, 8 * q + (int)grp, 64);
+            const uint32_t s = s0 + 8 * q + grp, c1 = (end + 3u) >> 2;
+            const uint4 *ent = reinterpret_cast<const uint4 *>(entries + (size_t)s * PG.region);
+            for (uint32_t c = (start >> 2) + 8u + gl;; c += 8u) {
+                const bool act = c < c1;
+                if (!__ballot(act)) break;
+                if (act) resolve(s, c, start, end, ent[c]);
+            }
+        }
+    };
+    const uint32_t step = kRunThreads;            // 16 wavefronts x 64 subgroups
+    uint32_t s0 = wv * 64u;
+    uint32_t stA, enA, stB, enB;
+    uint4 eA[8];
+    bounds(s0, stA, enA);
+    issue(s0, stA, enA, eA);
+    bounds(s0 + step, stB, enB);
+    for (; s0 < PG.n_sub; s0 += step) {
+        uint4 eB[8];
+        issue(s0 + step, stB, enB, eB);
+        uint32_t stC, enC;
+        bounds(s0 + 2 * step, stC, enC);
+        finish(s0, stA, enA, eA);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) eA[q] = eB[q];
+        stA = stB, enA = enB, stB = stC, enB = enC;
+    }
+}
+
+// ---------------------------------------------------------------------------
+enum FinMode { kFinClosedForm = 0, kFinMulti = 1, kFinLearned = 2 };
+
+// Several windows from one pass (ascending k' values).
+constexpr uint32_t kMaxWindows = 64;
+
+struct Windows {
+    uint32_t m;
+    uint32_t kp[kMaxWindows];
+};
+
+__device__ __forceinline__ uint32_t hist_bin(const uint32_t *row, uint32_t d)
+{
+    return (row[d >> 1] >> ((d & 1u) << 4)) & 0xFFFFu;
+}
+
+template <typename DT, int MODE>
+__global__ void __launch_bounds__(kFinThreads) k_run_finalize(Geo G, PartGeo PG, const DevState *__restrict__ st,
+                                                             uint32_t n, uint32_t kprime,
+                                                             const uint32_t *__restrict__ entries,
+                                                             const DT *__restrict__ dist, float *__restrict__ est,
+                                                             uint32_t *__restrict__ live_out,
+                                                             uint32_t *__restrict__ hist_out, Windows win,
+                                                             const unsigned long long *__restrict__ cum,
+                                                             const mlp::Packed *__restrict__ P,
+                                                             float *__restrict__ cf_out)
+{
+    extern __shared__ __attribute__((aligned(16))) uint32_t hist[];   // [2^sh][rowp] packed 16-bit bins
+    const uint32_t s = blockIdx.x, t = threadIdx.x;
+    const uint32_t h0 = s << PG.sh;
+    const uint32_t nh = min(1u << PG.sh, n - h0), nv = nh * G.g;
+    const uint32_t rowp = PG.rowp;
+    for (uint32_t q = t; q < nh * rowp; q += kFinThreads) hist[q] = 0;
+    __syncthreads();
+    {
+        const uint4 *ent = reinterpret_cast<const uint4 *>(entries + (size_t)s * PG.region);
+        const DT *dd = dist + (size_t)s * PG.region;
+        const uint32_t sl = PG.sl;
+        constexpr uint32_t U = 4;     // chunks in flight per thread
+        const uint32_t nch = (nv + 3u) >> 2;
+        for (uint32_t c0 = t; c0 < nch; c0 += U * kFinThreads) {
+            uint4 e4[U];
+            uint32_t d[U][4];
+#pragma unroll
+            for (uint32_t u = 0; u < U; ++u) {
+                const uint32_t c = c0 + u * kFinThreads;
+                if (c < nch) {
+                    e4[u] = ent[c];
+                    load4<DT>(dd + 4u * c, d[u]);
+                }
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < U; ++u) {
+                const uint32_t c = c0 + u * kFinThreads;
+                if (c >= nch) break;
+                const uint32_t e[4] = {e4[u].x, e4[u].y, e4[u].z, e4[u].w};
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    if (4u * c + m >= nv) break;
+                    const uint32_t dm = min(d[u][m], G.k);
+                    atomicAdd(&hist[(e[m] >> sl) * rowp + (dm >> 1)], 1u << ((dm & 1u) << 4));
+                }
+            }
+        }
+    }
+    __syncthreads();
+
+    if constexpr (MODE == kFinClosedForm) {
+        const uint64_t active_pool = pool_active(st, kprime);
+        for (uint32_t h = t; h < nh; h += kFinThreads) {
+            const uint32_t *row = hist + h * rowp;
+            uint32_t live = 0;
+            for (uint32_t d = 0; d < kprime; ++d) live += hist_bin(row, d);
+            est[h0 + h] = estimate_from_counts(G.g - live, G.N - active_pool, G.g, G.c);
+            if (live_out) live_out[h0 + h] = live;
+        }
+        if (hist_out) {
+            const uint32_t kp1 = G.k + 1;
+            uint32_t *out = hist_out + (size_t)h0 * kp1;
+            for (uint32_t q = t; q < nh * kp1; q += kFinThreads) {
+                const uint32_t h = q / kp1, d = q - h * kp1;
+                out[q] = hist_bin(hist + h * rowp, d);
+            }
+        }
+    } else if constexpr (MODE == kFinMulti) {
+        for (uint32_t h = t; h < nh; h += kFinThreads) {
+            const uint32_t *row = hist + h * rowp;
+            float *e = est + (size_t)(h0 + h) * win.m;
+            uint32_t live = 0, jw = 0;
+            for (uint32_t d = 0; d < G.k && jw < win.m; ++d) {
+                live += hist_bin(row, d);
+                while (jw < win.m && win.kp[jw] == d + 1) {
+                    e[jw] = estimate_from_counts(G.g - live, G.N - cum[d + 1], G.g, G.c);
+                    ++jw;
+                }
+            }
+        }
+    } else {
+        // Learned estimate: the closed form for window k and the packed
+        // histogram rows go out; the network runs in k_learned_rows, which
+        // keeps this streaming pass free of the network's register demand.
+        const uint64_t active_pool = pool_active(st, G.k);
+        for (uint32_t h = t; h < nh; h += kFinThreads) {
+            const uint32_t *row = hist + h * rowp;
+            uint32_t live = 0;
+            for (uint32_t d = 0; d < G.k; ++d) live += hist_bin(row, d);
+            cf_out[h0 + h] = estimate_from_counts(G.g - live, G.N - active_pool, G.g, G.c);
+        }
+        uint32_t *out = hist_out + (size_t)h0 * rowp;
+        for (uint32_t q = t; q < nh * rowp; q += kFinThreads) out[q] = hist[q];
+    }
+}
+
+// The learned estimate (window k) from packed histogram rows: per wavefront
+// 16 hosts' features, the network on the matrix cores, exp of its output
+// (the closed form where that is not finite).
+__global__ void __launch_bounds__(256) k_learned_rows(Geo G, const DevState *__restrict__ st, uint32_t n,
+                                                     uint32_t rowp, const uint32_t *__restrict__ rows,
+                                                     const float *__restrict__ cf, const mlp::Packed *__restrict__ P,
+                                                     float *__restrict__ est)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t xs_all[4][16 * mlp::LDS_STRIDE];
+    __shared__ __attribute__((aligned(16))) uint16_t a1_all[4][16 * mlp::LDS_STRIDE];
+    __shared__ float cf_w[4][16];
+    __shared__ uint32_t live_w[4][16];
+    const uint64_t active_pool = pool_active(st, G.k);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63, q = l >> 4, c = l & 15;
+    const uint32_t h0 = blockIdx.x * 64 + 16 * w;
+    const float fg = (float)G.g, occupancy = (float)active_pool / (float)G.N;
+    if (l < 16) {
+        const uint32_t h = h0 + l;
+        uint32_t live = 0;
+        float v = 0.f;
+        if (h < n) {
+            const uint32_t *row = rows + (size_t)h * rowp;
+            for (uint32_t d = 0; d < G.k; ++d) live += hist_bin(row, d);
+            v = cf[h];
+        }
+        live_w[w][l] = live;
+        cf_w[w][l] = v;
+    }
+    __syncthreads();
+    uint16_t *xs = xs_all[w];
+    for (int e = l; e < 16 * VATE_MLP_FEATURES; e += 64) {
+        const int m = e >> 6, f = e & 63;
+        const uint32_t h = h0 + m;
+        float x = 0.f;
+        if (h < n) {
+            if (f < (int)G.k)
+                x = (float)hist_bin(rows + (size_t)h * rowp, f) / fg;
+            else if (f == (int)G.k)
+                x = (float)live_w[w][m] / fg;
+            else if (f == (int)G.k + 1)
+                x = occupancy;
+            else if (f == (int)G.k + 2)
+                x = logf(fmaxf(cf_w[w][m], 1.0f)) * 0.0625f;
+        }
+        xs[m * mlp::LDS_STRIDE + f] = mlp::bf16_bits(x);
+    }
+    __syncthreads();
+    float r4[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) r4[r] = logf(fmaxf(cf_w[w][4 * q + r], 1.0f));
+    mlp::f32x4 z1[4], z2[4];
+    float a2v[4][4], o4[4];
+    mlp::forward16(P, xs, a1_all[w], r4, z1, z2, a2v, o4);
+    if (c < 4) {
+        const uint32_t h = h0 + 4 * q + c;
+        if (h < n) {
+            const float ex = expf(o4[c]);
+            est[h] = isfinite(ex) ? ex : cf_w[w][4 * q + c];
+        }
+    }
+}
+
+// Per-host windows from full histograms in memory (the fallback when the
+// partitioned lookups are not available for a geometry).
+__global__ void k_multi_from_hist(Geo G, uint32_t n, Windows win, const unsigned long long *__restrict__ cum,
+                                  const uint32_t *__restrict__ hist, float *__restrict__ est)
+{
+    const uint32_t h = blockIdx.x * blockDim.x + threadIdx.x;
+    if (h >= n) return;
+    const uint32_t *row = hist + (size_t)h * (G.k + 1);
+    uint32_t live = 0, j = 0;
+    for (uint32_t d = 0; d < G.k && j < win.m; ++d) {
+        live += row[d];
+        while (j < win.m && win.kp[j] == d + 1) {
+            est[(size_t)h * win.m + j] = estimate_from_counts(G.g - live, G.N - cum[d + 1], G.g, G.c);
+            ++j;
+        }
+    }
+}
+
+__global__ void k_census_prefix(Geo G, const DevState *__restrict__ st, unsigned long long *__restrict__ cum)
+{
+    if (threadIdx.x == 0) {
+        unsigned long long run = 0;
+        cum[0] = 0;
+        for (uint32_t d = 0; d < G.k; ++d) {
+            run += census_of(st)[d];
+            cum[d + 1] = run;
+        }
+    }
+}

@@ -382,6 +382,58 @@ def test_multi_window_estimates(w, k, c):
         assert np.all(np.abs(e[:, j] - r_est) <= _tol(r_est, ref.g)), kp
 
 
+@pytest.mark.parametrize("c,w,k,g,partition,n_hosts", [
+    (20, 8, 60, 1024, 0, 1000),     # 8 slices: one super-slice
+    (22, 4, 7, 100, 1, 777),        # g not a power of two, ragged last subgroup
+    (21, 16, 300, 512, 0, 500),     # k >= 255: 16-bit distances
+    (23, 8, 30, 2048, 0, 300),      # 64 slices (XCD mapping), g above the workgroup size
+    (20, 8, 100, 64, 1, 3000),      # blocks shorter than a slice (per-AT block lookup)
+    (18, 8, 5, 1, 0, 5000),         # g = 1: 1024 hosts per subgroup
+    (18, 8, 5, 3, 0, 2500),         # g = 3
+])
+def test_partitioned_geometries(c, w, k, g, partition, n_hosts):
+    """The partitioned lookups across their geometry cases: live counts,
+    histograms and estimates equal to the oracle (and bit-identical to the
+    direct gather) for several k', and the multi-window estimates too."""
+    rng = np.random.default_rng(c * 1000 + k + g)
+    cfg = Config(c, w, k, g, partition=partition, seed_a=c + g, seed_b=k)
+    gpu, ref = _pair(cfg)
+    hosts = rng.integers(0, 2**32, size=n_hosts, dtype=np.uint64).astype(np.uint32)
+    n_slices = min(k + 3, 40)
+    for t in range(n_slices):
+        n = int(rng.integers(1, 40_000))
+        pairs = np.stack([hosts[rng.integers(0, hosts.size, size=n)],
+                          rng.integers(0, 2**32, size=n, dtype=np.uint64).astype(np.uint32)], 1)
+        gpu.ingest(pairs)
+        ref.ingest(pairs)
+        gpu.close_slice()
+        ref.close_slice()
+    for kp in sorted({1, max(1, k // 2), k}):
+        _check_estimates(gpu, ref, hosts, kprime=kp, hist=(kp == k and k <= 256),
+                         what=f"c={c} w={w} k={k} g={g} k'={kp}")
+    if k > 256:   # beyond the direct gather's histogram limit: partitioned only
+        _, _, r_hist = ref.estimate(hosts, want_hist=True)
+        _, _, hh = gpu.estimate(hosts, want_hist=True, partitioned=True)
+        torch.cuda.synchronize()
+        assert np.array_equal(_u32(hh), r_hist)
+    kps = sorted({1, max(1, k // 3), max(1, k - 1), k})
+    est = gpu.estimate_windows(hosts, kps)
+    torch.cuda.synchronize()
+    e = est.cpu().numpy().astype(np.float64)
+    for j, kp in enumerate(kps):
+        r_est, _, _ = ref.estimate(hosts, kprime=kp)
+        assert np.all(np.abs(e[:, j] - r_est) <= _tol(r_est, ref.g)), kp
+    if k + 3 <= _lib.MLP_FEATURES:   # learned estimate: partitioned == fused direct, bit for bit
+        from paper_1812_00282_amd import learned as L
+        gen = torch.Generator().manual_seed(k)
+        theta = (torch.randn(_lib.MLP_PARAMS, generator=gen) * 0.05).cuda()
+        wts = L.pack(theta, L.new_weights())
+        d_learn, d_cf = L.estimate_learned(gpu, hosts, wts)
+        p_learn, p_cf = L.estimate_learned(gpu, hosts, wts, partitioned=True)
+        torch.cuda.synchronize()
+        assert torch.equal(d_cf, p_cf) and torch.equal(d_learn, p_learn)
+
+
 @pytest.mark.parametrize("w,k,c", [(4, 7, 12), (8, 60, 16), (16, 300, 16)])
 def test_vdre_matches_oracle_and_vate(w, k, c):
     """Distance-recorder counters (the paper's VDRE baseline, full-pool
