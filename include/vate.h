@@ -30,8 +30,10 @@
  *
  * Pool layout in HBM: AT p occupies bits [p*width, (p+1)*width) of the pool
  * byte array, little-endian (width 4: even p in the low nibble of byte p/2;
- * width 16: little-endian uint16 p).  Pool bytes = 2^c * width / 8, which
- * must be at least 16.
+ * width 16: little-endian uint16 p; any other width: counters packed back to
+ * back in little-endian 32-bit words, so 32 counters fill exactly `width`
+ * words - the paper's exact-width pool, Sec. 3 and Sec. 5).  Pool bytes =
+ * 2^c * width / 8.
  */
 #ifndef VATE_H
 #define VATE_H
@@ -54,9 +56,13 @@ extern "C" {
 /* Sketch parameters (Alg. 4 inputs c, k, k'; g of Sec. 4.1). */
 typedef struct vate_params {
     uint32_t log2_pool;  /* c: the pool holds N = 2^c ATs; 1 <= c <= 32 and
-                            N*width/8 >= 16 bytes; N >= 2k */
-    uint32_t width;      /* container bits per AT: 4, 8 or 16; the AT needs
-                            ceil(log2(2k+1)) bits (Sec. 3), so 2^width >= 2k+1 */
+                            N >= 2k; widths 4/8/16 need N*width/8 >= 16 bytes,
+                            other widths N >= 32 */
+    uint32_t width;      /* bits per AT, 1..16; the AT needs ceil(log2(2k+1))
+                            bits (Sec. 3), so 2^width >= 2k+1.  4, 8 and 16 use
+                            nibble/byte/short containers; any other width packs
+                            the ATs exactly (e.g. 7 bits at k = 60, 10 at
+                            k = 300) - the batched calls take 4/8/16 only */
     uint32_t k;          /* longest window, in slices (Sec. 1); k >= 1 */
     uint32_t g;          /* VATs per host (Sec. 4.1); 1 <= g <= 65535 */
     uint32_t partition;  /* 0: Eq. 9-10 blocks (Fig. 4: 2k-1 blocks of

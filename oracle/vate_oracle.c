@@ -168,7 +168,9 @@ o_vate *o_create(uint32_t c, uint32_t w, uint32_t k, uint32_t g,
 {
     if (c < 1 || c > 32 || k < 1 || g < 1 || counter > 1)
         return NULL;
-    if (w != 4 && w != 8 && w != 16)
+    if (w < 1 || w > 16)
+        return NULL;
+    if (w != 4 && w != 8 && w != 16 && c < 5)   /* exact packing: whole 32-bit words */
         return NULL;
     if (counter == 0 && (1ull << w) < 2ull * k + 1)   /* AT: ceil(log2(2k+1)) bits */
         return NULL;
@@ -403,10 +405,21 @@ void o_set_values(o_vate *s, const uint16_t *in, uint64_t t, uint32_t bact0,
     s->closed = closed;
 }
 
-/* Pool in the packed container layout: AT p occupies bits [p*w, p*w+w) of a
- * little-endian byte array (w=4: low nibble = even p; w=16: LE uint16). */
+/* Pool in the packed layout: AT p occupies bits [p*w, p*w+w) of a
+ * little-endian bit string (w=4: low nibble = even p; w=8: byte p; w=16: LE
+ * uint16; any other w: counters back to back).  out holds N*w/8 bytes. */
 void o_pack_pool(const o_vate *s, uint8_t *out)
 {
+    if (s->w != 4 && s->w != 8 && s->w != 16) {
+        memset(out, 0, (size_t)(s->N * s->w / 8));
+        for (uint64_t p = 0; p < s->N; p++)
+            for (uint32_t j = 0; j < s->w; j++)
+                if ((s->ATP[p] >> j) & 1u) {
+                    const uint64_t bit = p * s->w + j;
+                    out[bit >> 3] |= (uint8_t)(1u << (bit & 7));
+                }
+        return;
+    }
     if (s->w == 8) {
         for (uint64_t p = 0; p < s->N; p++)
             out[p] = (uint8_t)s->ATP[p];

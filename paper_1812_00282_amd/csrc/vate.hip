@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -45,7 +46,8 @@ __host__ __device__ __forceinline__ const unsigned long long *census_of(const De
 {
     return reinterpret_cast<const unsigned long long *>(st + 1);
 }
-constexpr int kMaxHistK = 256;      // per-host histogram limit (LDS budget)
+constexpr int kMaxHistK = 256;
+constexpr uint32_t kCensusLdsBins = 4096;   // census histogram bins kept in LDS      // per-host histogram limit (LDS budget)
 
 // State block layout: header, k census counters, then (256-byte aligned) the
 // activity bitmap of N bits.
@@ -70,7 +72,7 @@ int make_geo(const vate_params *p, Geo *G, const char **why)
     if (!p) { *why = "params is NULL"; return VATE_E_INVAL; }
     if (p->counter > 1) { *why = "counter must be 0 (AT) or 1 (DR)"; return VATE_E_INVAL; }
     if (p->log2_pool < 1 || p->log2_pool > 32) { *why = "log2_pool must be in [1, 32]"; return VATE_E_INVAL; }
-    if (p->width != 4 && p->width != 8 && p->width != 16) { *why = "width must be 4, 8 or 16"; return VATE_E_INVAL; }
+    if (p->width < 1 || p->width > 16) { *why = "width must be in [1, 16]"; return VATE_E_INVAL; }
     if (p->k < 1) { *why = "k must be >= 1"; return VATE_E_INVAL; }
     if (p->counter == 0 && (1ull << p->width) < 2ull * p->k + 1) {
         *why = "width too small: an AT needs 2^width >= 2k+1";
@@ -84,7 +86,9 @@ int make_geo(const vate_params *p, Geo *G, const char **why)
     if (p->partition > 1) { *why = "partition must be 0 or 1"; return VATE_E_INVAL; }
     uint64_t N = 1ull << p->log2_pool;
     if (N < 2ull * p->k) { *why = "pool smaller than 2k ATs"; return VATE_E_INVAL; }
-    if (N * p->width / 8 < 16) { *why = "pool smaller than 16 bytes"; return VATE_E_INVAL; }
+    const bool exact = p->width != 4 && p->width != 8 && p->width != 16;
+    if (!exact && N * p->width / 8 < 16) { *why = "pool smaller than 16 bytes"; return VATE_E_INVAL; }
+    if (exact && N < 32) { *why = "widths other than 4, 8, 16 need a pool of >= 32 counters"; return VATE_E_INVAL; }
     Geo g{};
     g.N = N;
     g.c = p->log2_pool;
@@ -96,7 +100,8 @@ int make_geo(const vate_params *p, Geo *G, const char **why)
     g.seed_b = p->seed_b;
     g.partition = p->partition;
     g.dr = p->counter;
-    const uint64_t E = 128 / p->width;   // ATs per 16-byte chunk
+    g.wb = p->width;
+    const uint64_t E = exact ? 32 : 128 / p->width;   // counters per 16-byte chunk / per word group
     if (p->partition == 0) {
         g.a = N / (g.twok - 1);
         g.thresh = 0;
@@ -121,10 +126,15 @@ int make_geo(const vate_params *p, Geo *G, const char **why)
 // ---------------------------------------------------------------------------
 // Container access.  AT p sits at bits [p*W, p*W+W) of the pool, little-endian.
 // ---------------------------------------------------------------------------
+#include "vate_exact.h"
+
+// W = 0: the exact width wb (counters packed back to back in 32-bit words).
 template <int W>
-__device__ __forceinline__ uint32_t load_at(const uint8_t *__restrict__ pool, uint32_t pid)
+__device__ __forceinline__ uint32_t load_at(const uint8_t *__restrict__ pool, uint32_t pid, uint32_t wb)
 {
-    if constexpr (W == 8) {
+    if constexpr (W == 0) {
+        return load_x(reinterpret_cast<const uint32_t *>(pool), pid, wb);
+    } else if constexpr (W == 8) {
         return pool[pid];
     } else if constexpr (W == 16) {
         return reinterpret_cast<const uint16_t *>(pool)[pid];
@@ -213,7 +223,10 @@ __device__ __forceinline__ void ingest_one(const Geo &G, uint8_t *__restrict__ p
     uint32_t pid = vat_pid(G, host_key(G, aip), vid);
     // SetAT stores the block's ACT; a DR is reset to 0
     uint32_t val = G.dr ? 0u : block_act(G, bact0, block_of(G, pid));
-    set_at<W>(pool, pid, val);
+    if constexpr (W == 0)
+        set_x(reinterpret_cast<uint32_t *>(pool), pid, G.wb, val);
+    else
+        set_at<W>(pool, pid, val);
 }
 
 template <int W, bool ALIGNED16>
@@ -245,7 +258,6 @@ __global__ void __launch_bounds__(256) k_ingest(Geo G, const uint32_t *__restric
 // In steady state most ATs hold 2k, so 16-byte chunks that are entirely
 // inactive are skipped after one compare.
 // ---------------------------------------------------------------------------
-constexpr uint32_t kCensusLdsBins = 4096;
 
 // The same pass writes the activity bitmap: bit p is set iff AT p is active
 // for the longest window k at the end of this slice (value != 2k and
@@ -414,7 +426,7 @@ __global__ void __launch_bounds__(256) k_estimate(Geo G, const uint8_t *__restri
                 ++live;
                 continue;
             }
-            const uint32_t d = value_dist(G, bact0, pid[u], load_at<W>(pool, pid[u]));
+            const uint32_t d = value_dist(G, bact0, pid[u], load_at<W>(pool, pid[u], G.wb));
             live += d < kprime;
             if (HIST) {
                 ++live_k;
@@ -489,7 +501,7 @@ __global__ void __launch_bounds__(256) k_estimate_learned(Geo G, const uint8_t *
 #pragma unroll
         for (int u = 0; u < kEstU; ++u) {
             if (!((byte[u] >> (pid[u] & 7u)) & 1u)) continue;
-            const uint32_t val = load_at<W>(pool, pid[u]);
+            const uint32_t val = load_at<W>(pool, pid[u], G.wb);
             const uint32_t d = value_dist(G, bact0, pid[u], val);
             ++live;
             atomicAdd(&my[(d >> 1) * 65 + lane], 1u << ((d & 1u) << 4));
@@ -692,27 +704,65 @@ static unsigned grid_for(uint64_t items, unsigned per_block, unsigned cap)
     return (unsigned)std::min<uint64_t>(b, cap);
 }
 
+// Width dispatch: 4, 8 and 16 bits use their containers; any other width is
+// the exact packing (template width 0).
+template <class F>
+static auto by_width(uint32_t w, F &&f)
+{
+    if (w == 4) return f(std::integral_constant<int, 4>{});
+    if (w == 8) return f(std::integral_constant<int, 8>{});
+    if (w == 16) return f(std::integral_constant<int, 16>{});
+    return f(std::integral_constant<int, 0>{});
+}
+
 template <int W>
 static void launch_init(vate_sketch *s, hipStream_t st)
 {
-    uint64_t nch = s->pool_bytes / 16;
-    k_init<W><<<grid_for(nch, 256, 8192), 256, 0, st>>>(s->G, reinterpret_cast<uint4 *>(s->pool), nch, s->st);
+    if constexpr (W == 0) {
+        const uint64_t ng = s->G.N / 32;
+        k_init_x<<<grid_for(ng, 256, 8192), 256, 0, st>>>(s->G, reinterpret_cast<uint32_t *>(s->pool), ng, s->st);
+    } else {
+        uint64_t nch = s->pool_bytes / 16;
+        k_init<W><<<grid_for(nch, 256, 8192), 256, 0, st>>>(s->G, reinterpret_cast<uint4 *>(s->pool), nch, s->st);
+    }
 }
 
 template <int W>
 static void launch_census(vate_sketch *s, hipStream_t st)
 {
-    uint64_t nch = s->pool_bytes / 16;
-    k_census<W><<<grid_for(nch, 256 * 4, 2048), 256, 0, st>>>(s->G, reinterpret_cast<const uint4 *>(s->pool),
-                                                               nch, s->st, s->bitmap);
+    if constexpr (W == 0) {
+        const uint64_t ng = s->G.N / 32;
+        k_census_x<<<grid_for(ng, 256, 4096), 256, 0, st>>>(s->G, reinterpret_cast<const uint32_t *>(s->pool), ng,
+                                                             s->st, s->bitmap);
+    } else {
+        uint64_t nch = s->pool_bytes / 16;
+        k_census<W><<<grid_for(nch, 256 * 4, 2048), 256, 0, st>>>(s->G, reinterpret_cast<const uint4 *>(s->pool),
+                                                                   nch, s->st, s->bitmap);
+    }
 }
 
 template <int W>
 static void launch_preserve(vate_sketch *s, hipStream_t st)
 {
     uint64_t threads = 2 * s->max_block_chunks;
-    k_preserve<W><<<grid_for(threads, 256, 1u << 30), 256, 0, st>>>(s->G, reinterpret_cast<uint4 *>(s->pool),
-                                                                     s->st, s->max_block_chunks);
+    if constexpr (W == 0)
+        k_preserve_x<<<grid_for(threads, 256, 1u << 30), 256, 0, st>>>(s->G, reinterpret_cast<uint32_t *>(s->pool),
+                                                                        s->st, s->max_block_chunks);
+    else
+        k_preserve<W><<<grid_for(threads, 256, 1u << 30), 256, 0, st>>>(s->G, reinterpret_cast<uint4 *>(s->pool),
+                                                                         s->st, s->max_block_chunks);
+}
+
+template <int W>
+static void launch_dr_maintain(vate_sketch *s, hipStream_t st)
+{
+    if constexpr (W == 0) {
+        const uint64_t ng = s->G.N / 32;
+        k_dr_maintain_x<<<grid_for(ng, 256, 8192), 256, 0, st>>>(s->G, reinterpret_cast<uint32_t *>(s->pool), ng);
+    } else {
+        const uint64_t nch = s->pool_bytes / 16;
+        k_dr_maintain<W><<<grid_for(nch, 256, 8192), 256, 0, st>>>(s->G, reinterpret_cast<uint4 *>(s->pool), nch);
+    }
 }
 
 template <int W>
@@ -727,32 +777,21 @@ static void launch_ingest(vate_sketch *s, const uint32_t *pairs, uint64_t n, hip
 
 static void dispatch_init(vate_sketch *s, hipStream_t st)
 {
-    if (s->p.width == 4) launch_init<4>(s, st);
-    else if (s->p.width == 8) launch_init<8>(s, st);
-    else launch_init<16>(s, st);
+    by_width(s->p.width, [&](auto W) { launch_init<decltype(W)::value>(s, st); });
 }
 
 static void dispatch_census(vate_sketch *s, hipStream_t st)
 {
-    if (s->p.width == 4) launch_census<4>(s, st);
-    else if (s->p.width == 8) launch_census<8>(s, st);
-    else launch_census<16>(s, st);
+    by_width(s->p.width, [&](auto W) { launch_census<decltype(W)::value>(s, st); });
 }
 
 static int advance(vate_sketch *s, hipStream_t st)
 {
     k_advance<<<1, 256, 0, st>>>(s->G, s->st);
-    if (s->G.dr) {
-        const uint64_t nch = s->pool_bytes / 16;
-        const unsigned grid = grid_for(nch, 256, 8192);
-        if (s->p.width == 4) k_dr_maintain<4><<<grid, 256, 0, st>>>(s->G, reinterpret_cast<uint4 *>(s->pool), nch);
-        else if (s->p.width == 8) k_dr_maintain<8><<<grid, 256, 0, st>>>(s->G, reinterpret_cast<uint4 *>(s->pool), nch);
-        else k_dr_maintain<16><<<grid, 256, 0, st>>>(s->G, reinterpret_cast<uint4 *>(s->pool), nch);
-    } else {
-        if (s->p.width == 4) launch_preserve<4>(s, st);
-        else if (s->p.width == 8) launch_preserve<8>(s, st);
-        else launch_preserve<16>(s, st);
-    }
+    if (s->G.dr)
+        by_width(s->p.width, [&](auto W) { launch_dr_maintain<decltype(W)::value>(s, st); });
+    else
+        by_width(s->p.width, [&](auto W) { launch_preserve<decltype(W)::value>(s, st); });
     s->closed = 0;
     return check_launch(s, "advance/preserve");
 }
@@ -790,8 +829,9 @@ static bool part_geo(const vate_sketch *s, uint64_t n, PartGeo *out)
 {
     const Geo &G = s->G;
     const uint32_t w = s->p.width;
-    const uint32_t wlog = w == 4 ? 2u : (w == 8 ? 3u : 4u);
-    uint32_t sl = kSliceBytesLog2 + 3u - wlog;          // 2^sl ATs of w bits = 128 KiB
+    uint32_t wlog = 0;                                  // ceil(log2 w)
+    while ((1u << wlog) < w) ++wlog;
+    uint32_t sl = kSliceBytesLog2 + 3u - wlog;          // the most ATs of w bits in 128 KiB, a power of two
     if (sl > G.c) sl = G.c;
     const uint64_t ns = G.N >> sl;
     if (ns > kRunMaxSlices) return false;
@@ -803,24 +843,30 @@ static bool part_geo(const vate_sketch *s, uint64_t n, PartGeo *out)
     p.xcd = p.n_super >= 8 ? 1u : 0u;
     p.rowp = (G.k + 2u) / 2u;
     p.dbytes = G.k < 255 ? 1u : 2u;
-    const uint64_t nsp = (ns + 3) & ~3ull;
-    int sh = (int)kRunMaxHostsLog2;
-    for (; sh >= 0; --sh) {
-        const uint64_t hosts = 1ull << sh, vats = hosts * G.g;
-        const uint64_t lds = 4 * (nsp + ((hosts + 3) & ~3ull) + vats);
-        if (vats <= kRunMaxEntries && lds <= kRunLdsBudget && hosts * p.rowp * 4 <= kFinHistBytes) break;
-    }
-    if (sh < 0) return false;
-    p.sh = (uint32_t)sh;
-    p.n_sub = (uint32_t)((n + (1ull << sh) - 1) >> sh);
-    p.vats = (1u << sh) * G.g;
-    p.region = (p.vats + 63u) & ~63u;
+    // Hosts per subgroup: the largest count whose VATs fit the scatter's
+    // registers, whose padded sorted entries (+ 16-bit slice counters, keys)
+    // fit its LDS, and whose histograms fit the finalize's LDS.
+    const uint64_t nsp = (((ns + 1) >> 1) + 3) & ~3ull;
+    auto lds_for = [&](uint64_t hosts) {
+        const uint64_t cap = (hosts * G.g + 3 * ns + 3) & ~3ull;
+        return 4 * (nsp + ((hosts + 3) & ~3ull) + cap);
+    };
+    uint64_t hosts = kRunMaxHosts;
+    hosts = std::min<uint64_t>(hosts, kRunMaxEntries / G.g);
+    hosts = std::min<uint64_t>(hosts, kFinHistBytes / (4ull * p.rowp));
+    while (hosts > 0 && lds_for(hosts) > kRunLdsBudget) --hosts;
+    if (hosts == 0) return false;
+    p.hosts = (uint32_t)hosts;
+    p.n_sub = (uint32_t)((n + hosts - 1) / hosts);
+    p.vats = (uint32_t)hosts * G.g;
+    p.cap = (uint32_t)((p.vats + 3ull * ns + 3) & ~3ull);
+    p.region = (p.cap + 63u) & ~63u;
     p.dq = kRunThreads / G.g;
     p.dr = kRunThreads % G.g;
     p.fast = G.a >= (1ull << sl) ? 1u : 0u;
-    p.lds_scatter = (uint32_t)(4 * (nsp + (((1ull << sh) + 3) & ~3ull) + p.vats));
+    p.lds_scatter = (uint32_t)lds_for(hosts);
     p.lds_lookup = (uint32_t)(((((uint64_t)w << sl) >> 3) + 15) & ~15ull);
-    p.lds_final = (1u << sh) * p.rowp * 4u;
+    p.lds_final = p.hosts * p.rowp * 4u;
     *out = p;
     return true;
 }
@@ -851,7 +897,7 @@ static RunWs run_ws(const PartGeo &pg, uint32_t k, void *base, bool learned = fa
     w.cum = reinterpret_cast<unsigned long long *>(p + off);
     off += align256((size_t)(k + 1) * 8);
     w.rows = reinterpret_cast<uint32_t *>(p + off);
-    if (learned) off += align256(((size_t)pg.n_sub << pg.sh) * pg.rowp * 4);
+    if (learned) off += align256((size_t)pg.n_sub * pg.hosts * pg.rowp * 4);
     w.bytes = off;
     return w;
 }
@@ -884,7 +930,7 @@ static int launch_part_typed(vate_sketch *s, const PartGeo &pg, const RunWs &w, 
                                                                           w.table, dist);
     if (MODE == kFinMulti) k_census_prefix<<<1, 64, 0, st>>>(s->G, s->st, w.cum);
     k_run_finalize<DT, MODE><<<pg.n_sub, kFinThreads, pg.lds_final, st>>>(
-        s->G, pg, s->st, n, kprime, w.entries, dist, est, live, MODE == kFinLearned ? w.rows : hist, win, w.cum,
+        s->G, pg, s->st, n, kprime, w.entries, dist, w.table, est, live, MODE == kFinLearned ? w.rows : hist, win, w.cum,
         static_cast<const mlp::Packed *>(weights), cf);
     if (MODE == kFinLearned)
         k_learned_rows<<<(n + 63) / 64, 256, 0, st>>>(s->G, s->st, n, pg.rowp, w.rows, cf,
@@ -908,11 +954,10 @@ static int launch_part_w(vate_sketch *s, const PartGeo &pg, void *ws, const uint
                          uint32_t kprime, float *est, uint32_t *live, uint32_t *hist, const Windows &win,
                          const void *weights, float *cf, hipStream_t st)
 {
-    if (s->p.width == 4)
-        return launch_part<4, MODE>(s, pg, ws, hosts, n, kprime, est, live, hist, win, weights, cf, st);
-    if (s->p.width == 8)
-        return launch_part<8, MODE>(s, pg, ws, hosts, n, kprime, est, live, hist, win, weights, cf, st);
-    return launch_part<16, MODE>(s, pg, ws, hosts, n, kprime, est, live, hist, win, weights, cf, st);
+    return by_width(s->p.width, [&](auto W) {
+        return launch_part<decltype(W)::value, MODE>(s, pg, ws, hosts, n, kprime, est, live, hist, win, weights, cf,
+                                                     st);
+    });
 }
 
 extern "C" {
@@ -952,7 +997,8 @@ int vate_create(const vate_params *p, void *pool_dev, void *state_dev, void *str
     uint64_t maxb = 0;
     for (uint32_t i = 0; i < G.twok; ++i)
         maxb = std::max<uint64_t>(maxb, block_start(G, i + 1) - block_start(G, i));
-    const uint64_t E = 128 / p->width;
+    const bool exact = p->width != 4 && p->width != 8 && p->width != 16;
+    const uint64_t E = exact ? 32 : 128 / p->width;      // counters per word group / 16-byte chunk
     s->max_block_chunks = (maxb + E - 1) / E + 1;
     s->closed = 0;
     s->dead = 0;
@@ -979,9 +1025,7 @@ int vate_ingest(vate_sketch *s, const uint32_t *pairs_dev, size_t n, void *strea
         if (rc != VATE_OK) return rc;
     }
     if (n == 0) return VATE_OK;
-    if (s->p.width == 4) launch_ingest<4>(s, pairs_dev, n, st);
-    else if (s->p.width == 8) launch_ingest<8>(s, pairs_dev, n, st);
-    else launch_ingest<16>(s, pairs_dev, n, st);
+    by_width(s->p.width, [&](auto W) { launch_ingest<decltype(W)::value>(s, pairs_dev, n, st); });
     return check_launch(s, "ingest");
 }
 
@@ -1018,9 +1062,9 @@ int vate_estimate(vate_sketch *s, const uint32_t *hosts_dev, size_t n_hosts, uin
         return fail(s, VATE_E_INVAL, "hosts/est/live/hist must be non-NULL (live, hist may be NULL) and 4-byte aligned");
     hipStream_t st = static_cast<hipStream_t>(stream);
     const uint32_t n = (uint32_t)n_hosts;
-    if (s->p.width == 4) launch_estimate<4>(s, hosts_dev, n, kprime, est_dev, live_dev, hist_dev, st);
-    else if (s->p.width == 8) launch_estimate<8>(s, hosts_dev, n, kprime, est_dev, live_dev, hist_dev, st);
-    else launch_estimate<16>(s, hosts_dev, n, kprime, est_dev, live_dev, hist_dev, st);
+    by_width(s->p.width, [&](auto W) {
+        launch_estimate<decltype(W)::value>(s, hosts_dev, n, kprime, est_dev, live_dev, hist_dev, st);
+    });
     return check_launch(s, "estimate");
 }
 
@@ -1057,9 +1101,9 @@ int vate_estimate_ws(vate_sketch *s, const uint32_t *hosts_dev, size_t n_hosts, 
     if (!part_geo(s, n, &pg)) {      // outside the partitioned limits: direct gather
         if (hist_dev && s->p.k > (uint32_t)kMaxHistK)
             return fail(s, VATE_E_UNSUPPORTED, "per-host histogram of this geometry needs k <= 256");
-        if (s->p.width == 4) launch_estimate<4>(s, hosts_dev, n, kprime, est_dev, live_dev, hist_dev, st);
-        else if (s->p.width == 8) launch_estimate<8>(s, hosts_dev, n, kprime, est_dev, live_dev, hist_dev, st);
-        else launch_estimate<16>(s, hosts_dev, n, kprime, est_dev, live_dev, hist_dev, st);
+        by_width(s->p.width, [&](auto W) {
+            launch_estimate<decltype(W)::value>(s, hosts_dev, n, kprime, est_dev, live_dev, hist_dev, st);
+        });
         return check_launch(s, "estimate_ws");
     }
     const int rc = launch_part_w<kFinClosedForm>(s, pg, workspace_dev, hosts_dev, n, kprime, est_dev, live_dev,
@@ -1090,9 +1134,9 @@ int vate_estimate_learned_ws(vate_sketch *s, const uint32_t *hosts_dev, size_t n
     const uint32_t n = (uint32_t)n_hosts;
     PartGeo pg;
     if (!part_geo(s, n, &pg)) {      // outside the partitioned limits: fused direct gather
-        if (s->p.width == 4) launch_estimate_learned<4>(s, hosts_dev, n, weights_dev, est_dev, est_cf_dev, st);
-        else if (s->p.width == 8) launch_estimate_learned<8>(s, hosts_dev, n, weights_dev, est_dev, est_cf_dev, st);
-        else launch_estimate_learned<16>(s, hosts_dev, n, weights_dev, est_dev, est_cf_dev, st);
+        by_width(s->p.width, [&](auto W) {
+            launch_estimate_learned<decltype(W)::value>(s, hosts_dev, n, weights_dev, est_dev, est_cf_dev, st);
+        });
         return check_launch(s, "estimate_learned_ws");
     }
     const int rc = launch_part_w<kFinLearned>(s, pg, workspace_dev, hosts_dev, n, s->p.k, est_dev, nullptr, nullptr,
@@ -1151,9 +1195,9 @@ int vate_estimate_multi_ws(vate_sketch *s, const uint32_t *hosts_dev, size_t n_h
     uint32_t *hist = reinterpret_cast<uint32_t *>(ws);
     unsigned long long *cum = reinterpret_cast<unsigned long long *>(ws + align256((size_t)n * (s->p.k + 1) * 4));
     // the direct gather for window k fills the per-host histograms (est is scratch here)
-    if (s->p.width == 4) launch_estimate<4>(s, hosts_dev, n, s->p.k, est_dev, nullptr, hist, st);
-    else if (s->p.width == 8) launch_estimate<8>(s, hosts_dev, n, s->p.k, est_dev, nullptr, hist, st);
-    else launch_estimate<16>(s, hosts_dev, n, s->p.k, est_dev, nullptr, hist, st);
+    by_width(s->p.width, [&](auto W) {
+        launch_estimate<decltype(W)::value>(s, hosts_dev, n, s->p.k, est_dev, nullptr, hist, st);
+    });
     k_census_prefix<<<1, 64, 0, st>>>(s->G, s->st, cum);
     k_multi_from_hist<<<grid_for(n, 256, 1u << 30), 256, 0, st>>>(s->G, n, win, cum, hist, est_dev);
     return check_launch(s, "estimate_multi_ws");
@@ -1183,9 +1227,9 @@ int vate_estimate_learned(vate_sketch *s, const uint32_t *hosts_dev, size_t n_ho
         return fail(s, VATE_E_INVAL, "hosts/est/est_cf must be 4-byte and weights 256-byte aligned, non-NULL");
     hipStream_t st = static_cast<hipStream_t>(stream);
     const uint32_t n = (uint32_t)n_hosts;
-    if (s->p.width == 4) launch_estimate_learned<4>(s, hosts_dev, n, weights_dev, est_dev, est_cf_dev, st);
-    else if (s->p.width == 8) launch_estimate_learned<8>(s, hosts_dev, n, weights_dev, est_dev, est_cf_dev, st);
-    else launch_estimate_learned<16>(s, hosts_dev, n, weights_dev, est_dev, est_cf_dev, st);
+    by_width(s->p.width, [&](auto W) {
+        launch_estimate_learned<decltype(W)::value>(s, hosts_dev, n, weights_dev, est_dev, est_cf_dev, st);
+    });
     return check_launch(s, "estimate_learned");
 }
 

@@ -96,6 +96,8 @@ int vate_batch_create(vate_sketch *const *sketches, uint32_t n, void *batch_dev,
         return VATE_E_INVAL;
     for (uint32_t i = 0; i < n; ++i) {
         if (!sketches[i] || sketches[i]->dead) return VATE_E_INVAL;
+        const uint32_t w = sketches[i]->p.width;
+        if (w != 4 && w != 8 && w != 16) return VATE_E_UNSUPPORTED;   // batched kernels use 4/8/16-bit containers
         for (uint32_t j = 0; j < i; ++j)
             if (sketches[j] == sketches[i]) return VATE_E_INVAL;
     }

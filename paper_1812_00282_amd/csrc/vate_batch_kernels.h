@@ -234,7 +234,7 @@ __device__ __forceinline__ uint32_t batch_host_live(const BatchItem &it, uint32_
                 ++live;
                 continue;
             }
-            const uint32_t d = value_dist(G, bact0, pid[u], load_at<W>(it.pool, pid[u]));
+            const uint32_t d = value_dist(G, bact0, pid[u], load_at<W>(it.pool, pid[u], it.G.wb));
             live += d < it.kprime;
         }
     }

@@ -77,6 +77,7 @@ struct Geo {
     uint32_t seed_a, seed_b;
     uint32_t partition;  // 0: Eq. 9-10, 1: Fig. 5
     uint32_t dr;         // 0: asynchronous timestamps; 1: distance recorders (VDRE)
+    uint32_t wb;         // counter width in bits
     uint32_t base1;      // Fig. 5: index of the first (a'+1)-sized block, 2k - b'
     uint32_t fast_blocks;// every block but the last holds >= one 16-byte chunk
     Div32 div_a;         // divide by a (Eq. 9) or a' (Fig. 5)

@@ -6,13 +6,15 @@
 // The direct gather reads one random cache line per VAT anywhere in the
 // pool, so it is bound by line fills from beyond L2.  Here:
 //
-//  k_run_scatter  one workgroup per subgroup of 2^sh hosts.  Hashes the
+//  k_run_scatter  one workgroup per subgroup of hosts.  Hashes the
 //                 subgroup's VATs once (pids stay in registers), counts them
 //                 per pool slice in LDS, places them by an LDS counting sort
 //                 and copies the sorted entries (host within subgroup, AT
 //                 within slice) to the workspace as one coalesced stream.
-//                 The start of every (subgroup, slice) run goes to a u16
-//                 table laid out [super-slice][subgroup][slice in super].
+//                 Every (subgroup, slice) run starts on a 4-entry boundary
+//                 (padded with kRunPad), so no 16-byte chunk is shared by two
+//                 slices.  Run starts go to a u16 table laid out
+//                 [super-slice][subgroup][slice in super].
 //  k_run_lookup   one workgroup per pool slice (128 KiB of ATs, held in LDS).
 //                 Walks that slice's run in every subgroup and writes each
 //                 VAT's distance (Eq. 5, CheckAT; k = inactive for window k)
@@ -34,7 +36,8 @@ constexpr uint32_t kRunMaxEntries = kRunThreads * kRunPerThread; // VATs per sub
 constexpr uint32_t kRunLdsBudget = 152u * 1024u;                // scatter LDS ceiling (bytes)
 constexpr uint32_t kSliceBytesLog2 = 17;                        // pool bytes per slice: 128 KiB
 constexpr uint32_t kRunMaxSlices = 8192;                        // pools up to 1 GiB
-constexpr uint32_t kRunMaxHostsLog2 = 10;                       // hosts per subgroup <= 1024
+constexpr uint32_t kRunMaxHosts = 1024;                         // hosts per subgroup
+constexpr uint32_t kRunPad = 0xFFFFFFFFu;                       // padding entry (never a real one: <= 28 bits)
 constexpr uint32_t kSuper = 8;                                  // slices per super-slice
 constexpr uint32_t kFinThreads = 256;
 constexpr uint32_t kFinHistBytes = 64u * 1024u;                 // per-subgroup histogram ceiling
@@ -44,10 +47,11 @@ struct PartGeo {
     uint32_t n_slices;    // N >> sl
     uint32_t sub;         // slices per super-slice, min(8, n_slices)
     uint32_t n_super;     // n_slices / sub
-    uint32_t sh;          // hosts per subgroup = 2^sh
+    uint32_t hosts;       // hosts per subgroup
     uint32_t n_sub;       // subgroups
-    uint32_t vats;        // 2^sh * g
-    uint32_t region;      // entries between subgroup regions (vats rounded up to 64)
+    uint32_t vats;        // hosts * g
+    uint32_t cap;         // padded entries per subgroup at most: vats + 3 n_slices, rounded up to 4
+    uint32_t region;      // entries between subgroup regions (cap rounded up to 64)
     uint32_t dq, dr;      // kRunThreads = dq * g + dr
     uint32_t fast;        // every block holds >= 2^sl ATs: a slice meets at most two blocks
     uint32_t rowp;        // u32 words per packed 16-bit histogram row, ceil((k + 1) / 2)
@@ -57,22 +61,25 @@ struct PartGeo {
 };
 
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t pad4(uint32_t x) { return (x + 3u) & ~3u; }
+
 __global__ void __launch_bounds__(kRunThreads) k_run_scatter(Geo G, PartGeo PG, const uint32_t *__restrict__ hosts,
                                                             uint32_t n, uint32_t *__restrict__ entries,
                                                             uint16_t *__restrict__ table)
 {
     extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
     __shared__ uint32_t wsum[kRunThreads / 64];
-    const uint32_t nsp = (PG.n_slices + 3u) & ~3u;
-    const uint32_t nkp = ((1u << PG.sh) + 3u) & ~3u;
-    uint32_t *cnt = lds;                  // [n_slices] counts, then cursors
-    uint32_t *keys = lds + nsp;           // [2^sh] host keys
-    uint32_t *sorted = keys + nkp;        // [vats] entries sorted by slice
+    const uint32_t nwords = (PG.n_slices + 1u) >> 1;       // two 16-bit counters per word
+    const uint32_t nsp = (nwords + 3u) & ~3u;
+    const uint32_t nkp = (PG.hosts + 3u) & ~3u;
+    uint32_t *cnt = lds;                  // slice counts, then cursors (16-bit pairs)
+    uint32_t *keys = lds + nsp;           // host keys
+    uint32_t *sorted = keys + nkp;        // entries sorted by slice, runs padded to 4
     const uint32_t s = blockIdx.x, t = threadIdx.x;
-    const uint32_t h0 = s << PG.sh;
-    const uint32_t nh = min(1u << PG.sh, n - h0);
+    const uint32_t h0 = s * PG.hosts;
+    const uint32_t nh = min(PG.hosts, n - h0);
     const uint32_t nv = nh * G.g;
-    for (uint32_t b = t; b < PG.n_slices; b += kRunThreads) cnt[b] = 0;
+    for (uint32_t q = t; q < nsp; q += kRunThreads) cnt[q] = 0;
     for (uint32_t h = t; h < nh; h += kRunThreads) keys[h] = host_key(G, hosts[h0 + h]);
     __syncthreads();
 
@@ -86,7 +93,8 @@ __global__ void __launch_bounds__(kRunThreads) k_run_scatter(Geo G, PartGeo PG, 
         for (uint32_t j = 0; j < kRunPerThread; ++j) {
             if (t + j * kRunThreads < nv) {
                 pid[j] = vat_pid(G, keys[host], i);
-                atomicAdd(&cnt[pid[j] >> sl], 1u);
+                const uint32_t b = pid[j] >> sl;
+                atomicAdd(&cnt[b >> 1], 1u << ((b & 1u) << 4));
             }
             i += PG.dr;
             host += PG.dq;
@@ -98,12 +106,16 @@ __global__ void __launch_bounds__(kRunThreads) k_run_scatter(Geo G, PartGeo PG, 
     }
     __syncthreads();
 
-    // Exclusive scan of the slice counts; thread t owns counters [t per, (t+1) per).
-    const uint32_t per = (PG.n_slices + kRunThreads - 1) / kRunThreads;
-    const uint32_t b0 = t * per;
+    // Exclusive scan of the padded slice counts; thread t owns whole counter
+    // words [t pw, (t+1) pw), i.e. slices [2 t pw, 2 (t+1) pw).
+    const uint32_t pw = (nwords + kRunThreads - 1) / kRunThreads;
+    const uint32_t w0 = t * pw;
     uint32_t mine = 0;
-    for (uint32_t q = 0; q < per; ++q)
-        if (b0 + q < PG.n_slices) mine += cnt[b0 + q];
+    for (uint32_t q = 0; q < pw; ++q)
+        if (w0 + q < nwords) {
+            const uint32_t v = cnt[w0 + q];
+            mine += pad4(v & 0xFFFFu) + pad4(v >> 16);
+        }
     const uint32_t lane = t & 63u, wv = t >> 6;
     uint32_t incl = mine;
 #pragma unroll
@@ -115,16 +127,23 @@ __global__ void __launch_bounds__(kRunThreads) k_run_scatter(Geo G, PartGeo PG, 
     __syncthreads();
     uint32_t run = incl - mine;
     for (uint32_t q = 0; q < wv; ++q) run += wsum[q];
-    for (uint32_t q = 0; q < per; ++q) {
-        const uint32_t b = b0 + q;
-        if (b >= PG.n_slices) break;
-        const uint32_t c = cnt[b];
-        cnt[b] = run;
-        const uint32_t B = b / PG.sub, jj = b - B * PG.sub;
-        table[((size_t)B * PG.n_sub + s) * PG.sub + jj] = (uint16_t)run;
-        run += c;
+    for (uint32_t q = 0; q < pw; ++q) {
+        const uint32_t w = w0 + q;
+        if (w >= nwords) break;
+        const uint32_t v = cnt[w], c0 = v & 0xFFFFu, c1 = v >> 16;
+        const uint32_t p0 = run, p1 = run + pad4(c0);
+        run = p1 + pad4(c1);
+        cnt[w] = p0 | (p1 << 16);
+        for (uint32_t x = p0 + c0; x < p1; ++x) sorted[x] = kRunPad;
+        for (uint32_t x = p1 + c1; x < run; ++x) sorted[x] = kRunPad;
+        const uint32_t b = 2u * w;
+        table[((size_t)(b / PG.sub) * PG.n_sub + s) * PG.sub + b % PG.sub] = (uint16_t)p0;
+        if (b + 1 < PG.n_slices)
+            table[((size_t)((b + 1) / PG.sub) * PG.n_sub + s) * PG.sub + (b + 1) % PG.sub] = (uint16_t)p1;
     }
-    if (t == 0) table[((size_t)PG.n_super * PG.n_sub + s) * PG.sub] = (uint16_t)nv;
+    uint32_t total = 0;
+    for (uint32_t q = 0; q < kRunThreads / 64; ++q) total += wsum[q];
+    if (t == 0) table[((size_t)PG.n_super * PG.n_sub + s) * PG.sub] = (uint16_t)total;
     __syncthreads();
 
     {
@@ -132,7 +151,8 @@ __global__ void __launch_bounds__(kRunThreads) k_run_scatter(Geo G, PartGeo PG, 
 #pragma unroll
         for (uint32_t j = 0; j < kRunPerThread; ++j) {
             if (t + j * kRunThreads < nv) {
-                const uint32_t slot = atomicAdd(&cnt[pid[j] >> sl], 1u);
+                const uint32_t b = pid[j] >> sl, sh16 = (b & 1u) << 4;
+                const uint32_t slot = (atomicAdd(&cnt[b >> 1], 1u << sh16) >> sh16) & 0xFFFFu;
                 sorted[slot] = (host << sl) | (pid[j] & mask);
             }
             i += PG.dr;
@@ -144,11 +164,8 @@ __global__ void __launch_bounds__(kRunThreads) k_run_scatter(Geo G, PartGeo PG, 
         }
     }
     __syncthreads();
-    uint32_t *out = entries + (size_t)s * PG.region;
-    const uint32_t n4 = nv >> 2;
-    for (uint32_t q = t; q < n4; q += kRunThreads)
-        reinterpret_cast<uint4 *>(out)[q] = reinterpret_cast<const uint4 *>(sorted)[q];
-    for (uint32_t q = (n4 << 2) + t; q < nv; q += kRunThreads) out[q] = sorted[q];
+    uint4 *out = reinterpret_cast<uint4 *>(entries + (size_t)s * PG.region);
+    for (uint32_t q = t; q < total / 4; q += kRunThreads) out[q] = reinterpret_cast<const uint4 *>(sorted)[q];
 }
 
 // ---------------------------------------------------------------------------
@@ -192,7 +209,7 @@ __global__ void __launch_bounds__(kRunThreads) k_run_lookup(Geo G, PartGeo PG, c
     }
     const uint32_t b = B * PG.sub + j;
     const uint32_t sl = PG.sl, mask = (1u << sl) - 1u;
-    const uint32_t nbytes = (uint32_t)(((uint64_t)W << sl) >> 3);
+    const uint32_t nbytes = (uint32_t)(((uint64_t)(W ? W : G.wb) << sl) >> 3);
     const uint8_t *src = pool + (uint64_t)b * nbytes;
     if ((nbytes & 15u) == 0) {
         for (uint32_t q = threadIdx.x; q < nbytes / 16; q += kRunThreads)
@@ -215,7 +232,7 @@ __global__ void __launch_bounds__(kRunThreads) k_run_lookup(Geo G, PartGeo PG, c
         act1 = block_act(G, bact0, bid0 + 1 < G.twok ? bid0 + 1 : bid0);
     }
     auto dist_of = [&](uint32_t local) -> uint32_t {
-        const uint32_t v = load_at<W>(at, local);
+        const uint32_t v = load_at<W>(at, local, G.wb);
         if (v == inact) return G.k;
         uint32_t d;
         if (G.dr) {
@@ -236,27 +253,12 @@ __global__ void __launch_bounds__(kRunThreads) k_run_lookup(Geo G, PartGeo PG, c
     const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
     const uint32_t grp = lane >> 3, gl = lane & 7u;
     const size_t row = (size_t)B * PG.n_sub, next_row = (size_t)(B + 1) * PG.n_sub;
-    auto resolve = [&](uint32_t s, uint32_t c, uint32_t start, uint32_t end, const uint4 &e4) {
-        DT *dst = dist + (size_t)s * PG.region;
-        const uint32_t e[4] = {e4.x, e4.y, e4.z, e4.w};
-        uint32_t d[4];
-        bool full = true;
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            const uint32_t idx = 4u * c + m;
-            const bool valid = idx >= start && idx < end;
-            full = full && valid;
-            d[m] = valid ? dist_of(e[m] & mask) : 0u;
-        }
-        if (full) {
-            store4<DT>(dst + 4u * c, d);
-        } else {
-#pragma unroll
-            for (int m = 0; m < 4; ++m) {
-                const uint32_t idx = 4u * c + m;
-                if (idx >= start && idx < end) dst[idx] = (DT)d[m];
-            }
-        }
+    // Runs start and end on 4-entry boundaries: every chunk belongs to one
+    // run.  Padding entries get a distance too; the finalize skips them.
+    auto resolve = [&](uint32_t s, uint32_t c, const uint4 &e4) {
+        const uint32_t d[4] = {dist_of(e4.x & mask), dist_of(e4.y & mask), dist_of(e4.z & mask),
+                               dist_of(e4.w & mask)};
+        store4<DT>(dist + (size_t)s * PG.region + 4u * c, d);
     };
     // Software pipeline over groups of 64 subgroups: while group i is
     // resolved, the entries of group i + 1 and the run bounds of group i + 2
@@ -275,7 +277,7 @@ __global__ void __launch_bounds__(kRunThreads) k_run_lookup(Geo G, PartGeo PG, c
             const uint32_t start = __shfl(st_l, 8 * q + (int)grp, 64), end = __shfl(en_l, 8 * q + (int)grp, 64);
             const uint32_t c = (start >> 2) + gl;
             e4[q] = make_uint4(0u, 0u, 0u, 0u);
-            if (c < ((end + 3u) >> 2))
+            if (c < (end >> 2))
                 e4[q] = reinterpret_cast<const uint4 *>(entries + (size_t)(s0 + 8 * q + grp) * PG.region)[c];
         }
     };
@@ -284,16 +286,16 @@ __global__ void __launch_bounds__(kRunThreads) k_run_lookup(Geo G, PartGeo PG, c
         for (int q = 0; q < 8; ++q) {
             const uint32_t start = __shfl(st_l, 8 * q + (int)grp, 64), end = __shfl(en_l, 8 * q + (int)grp, 64);
             const uint32_t c = (start >> 2) + gl;
-            if (c < ((end + 3u) >> 2)) resolve(s0 + 8 * q + grp, c, start, end, e4[q]);
+            if (c < (end >> 2)) resolve(s0 + 8 * q + grp, c, e4[q]);
         }
         for (int q = 0; q < 8; ++q) {      // chunks beyond a run's first eight
             const uint32_t start = __shfl(st_l, 8 * q + (int)grp, 64), end = __shfl(en_l, 8 * q + (int)grp, 64);
-            const uint32_t s = s0 + 8 * q + grp, c1 = (end + 3u) >> 2;
+            const uint32_t s = s0 + 8 * q + grp, c1 = end >> 2;
             const uint4 *ent = reinterpret_cast<const uint4 *>(entries + (size_t)s * PG.region);
             for (uint32_t c = (start >> 2) + 8u + gl;; c += 8u) {
                 const bool act = c < c1;
                 if (!__ballot(act)) break;
-                if (act) resolve(s, c, start, end, ent[c]);
+                if (act) resolve(s, c, ent[c]);
             }
         }
     };
@@ -336,17 +338,19 @@ template <typename DT, int MODE>
 __global__ void __launch_bounds__(kFinThreads) k_run_finalize(Geo G, PartGeo PG, const DevState *__restrict__ st,
                                                              uint32_t n, uint32_t kprime,
                                                              const uint32_t *__restrict__ entries,
-                                                             const DT *__restrict__ dist, float *__restrict__ est,
+                                                             const DT *__restrict__ dist,
+                                                             const uint16_t *__restrict__ table, float *__restrict__ est,
                                                              uint32_t *__restrict__ live_out,
                                                              uint32_t *__restrict__ hist_out, Windows win,
                                                              const unsigned long long *__restrict__ cum,
                                                              const mlp::Packed *__restrict__ P,
                                                              float *__restrict__ cf_out)
 {
-    extern __shared__ __attribute__((aligned(16))) uint32_t hist[];   // [2^sh][rowp] packed 16-bit bins
+    extern __shared__ __attribute__((aligned(16))) uint32_t hist[];   // [hosts][rowp] packed 16-bit bins
     const uint32_t s = blockIdx.x, t = threadIdx.x;
-    const uint32_t h0 = s << PG.sh;
-    const uint32_t nh = min(1u << PG.sh, n - h0), nv = nh * G.g;
+    const uint32_t h0 = s * PG.hosts;
+    const uint32_t nh = min(PG.hosts, n - h0);
+    const uint32_t nvp = table[((size_t)PG.n_super * PG.n_sub + s) * PG.sub];   // padded entries
     const uint32_t rowp = PG.rowp;
     for (uint32_t q = t; q < nh * rowp; q += kFinThreads) hist[q] = 0;
     __syncthreads();
@@ -355,7 +359,7 @@ __global__ void __launch_bounds__(kFinThreads) k_run_finalize(Geo G, PartGeo PG,
         const DT *dd = dist + (size_t)s * PG.region;
         const uint32_t sl = PG.sl;
         constexpr uint32_t U = 4;     // chunks in flight per thread
-        const uint32_t nch = (nv + 3u) >> 2;
+        const uint32_t nch = nvp >> 2;
         for (uint32_t c0 = t; c0 < nch; c0 += U * kFinThreads) {
             uint4 e4[U];
             uint32_t d[U][4];
@@ -374,7 +378,7 @@ __global__ void __launch_bounds__(kFinThreads) k_run_finalize(Geo G, PartGeo PG,
                 const uint32_t e[4] = {e4[u].x, e4[u].y, e4[u].z, e4[u].w};
 #pragma unroll
                 for (int m = 0; m < 4; ++m) {
-                    if (4u * c + m >= nv) break;
+                    if (e[m] == kRunPad) continue;
                     const uint32_t dm = min(d[u][m], G.k);
                     atomicAdd(&hist[(e[m] >> sl) * rowp + (dm >> 1)], 1u << ((dm & 1u) << 4));
                 }

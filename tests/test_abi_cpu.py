@@ -37,7 +37,9 @@ def test_library_exports_every_declared_symbol():
 
 
 @pytest.mark.parametrize("bad", [
-    dict(log2_pool=0), dict(log2_pool=33), dict(width=5), dict(k=0),
+    dict(log2_pool=0), dict(log2_pool=33), dict(width=0), dict(width=17), dict(k=0),
+    dict(width=3, k=4),                                   # 2^3 < 2k+1
+    dict(log2_pool=4, width=5, k=2),                      # exact packing needs >= 32 counters
     dict(width=4, k=8), dict(width=8, k=128), dict(g=0), dict(g=65536),
     dict(partition=2), dict(log2_pool=3, k=3, width=4),   # 2^3 < 2k
     dict(log2_pool=4, width=4, k=1),                      # pool of 8 bytes < 16
@@ -59,6 +61,17 @@ def test_counter_kind_validated():
     assert _lib.lib().vate_state_bytes(ctypes.byref(p), ctypes.byref(pb), ctypes.byref(sb)) == _lib.VATE_E_INVAL
 
 
+def test_exact_widths_accepted():
+    """Any width of 1..16 bits that holds the counter's range is accepted;
+    widths other than 4/8/16 pack the counters exactly (the paper's pool:
+    ceil(log2(2k+1)) bits per AT, Sec. 3)."""
+    for k in (1, 2, 3, 60, 300, 1000):
+        w = (2 * k).bit_length()            # ceil(log2(2k+1))
+        assert state_bytes(Config(16, w, k, 64))[0] == (1 << 16) * w // 8
+        wd = k.bit_length()                 # ceil(log2(k+1)) for a DR
+        assert state_bytes(Config(16, wd, k, 64, counter=1))[0] == (1 << 16) * wd // 8
+
+
 def test_dr_width_rule():
     """A DR needs ceil(log2(k+1)) bits (Sec. 1), one fewer than an AT: k = 8 fits
     4-bit DRs but not 4-bit ATs."""
@@ -67,7 +80,8 @@ def test_dr_width_rule():
         state_bytes(Config(16, 4, 8, 64, counter=0))
 
 
-@pytest.mark.parametrize("c,w,k", [(16, 8, 4), (5, 4, 2), (28, 8, 60), (29, 16, 256), (32, 16, 300)])
+@pytest.mark.parametrize("c,w,k", [(16, 8, 4), (5, 4, 2), (28, 8, 60), (29, 16, 256), (32, 16, 300),
+                                   (28, 7, 60), (32, 10, 300), (5, 3, 2), (20, 13, 4000)])
 def test_state_bytes(c, w, k):
     pb, sb = state_bytes(Config(c, w, k, 64))
     assert pb == (1 << c) * w // 8

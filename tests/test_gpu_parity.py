@@ -96,11 +96,13 @@ def test_small_workload_every_slice():
 
 @pytest.mark.parametrize("partition", [0, 1])
 @pytest.mark.parametrize("w,k,c", [(4, 2, 12), (4, 7, 10), (8, 9, 13), (8, 100, 14),
-                                   (16, 129, 16), (16, 256, 17), (16, 1000, 16)])
+                                   (16, 129, 16), (16, 256, 17), (16, 1000, 16),
+                                   (2, 1, 8), (3, 3, 10), (5, 10, 12), (7, 60, 14), (10, 300, 16)])
 def test_widths_and_windows(w, k, c, partition):
-    """Every container width, windows across the LDS-histogram tiers
-    (k <= 64, <= 128, <= 256) and beyond (k = 1000, no histogram), both
-    partitions, for 2k+5 slices so that every block's ACT wraps."""
+    """Every container width and exact widths (ceil(log2(2k+1)) bits packed
+    back to back), windows across the LDS-histogram tiers (k <= 64, <= 128,
+    <= 256) and beyond (k = 1000, no histogram), both partitions, for 2k+5
+    slices so that every block's ACT wraps."""
     rng = np.random.default_rng(w * 100 + k + partition)
     cfg = Config(c, w, k, 64, partition=partition, seed_a=k, seed_b=w)
     gpu, ref = _pair(cfg)
@@ -128,7 +130,7 @@ def test_small_pool_per_element_blocks():
     """Pools whose blocks are shorter than a 16-byte chunk (the census and
     preservation take the per-AT block path) and 4-bit ATs packed 8 per word
     under heavy write contention."""
-    for c, w, k in [(5, 4, 2), (5, 4, 7), (4, 8, 3), (3, 16, 4), (6, 4, 5)]:
+    for c, w, k in [(5, 4, 2), (5, 4, 7), (4, 8, 3), (3, 16, 4), (6, 4, 5), (5, 3, 2), (6, 5, 7), (7, 9, 20)]:
         cfg = Config(c, w, k, 16, seed_a=c, seed_b=k)
         gpu, ref = _pair(cfg)
         rng = np.random.default_rng(c * 10 + k)
@@ -390,6 +392,8 @@ def test_multi_window_estimates(w, k, c):
     (20, 8, 100, 64, 1, 3000),      # blocks shorter than a slice (per-AT block lookup)
     (18, 8, 5, 1, 0, 5000),         # g = 1: 1024 hosts per subgroup
     (18, 8, 5, 3, 0, 2500),         # g = 3
+    (23, 7, 60, 1024, 0, 300),      # exact 7-bit ATs, 64 slices of 2^17
+    (21, 10, 300, 512, 1, 500),     # exact 10-bit ATs (slices of 2^16), 16-bit distances
 ])
 def test_partitioned_geometries(c, w, k, g, partition, n_hosts):
     """The partitioned lookups across their geometry cases: live counts,
@@ -434,14 +438,14 @@ def test_partitioned_geometries(c, w, k, g, partition, n_hosts):
         assert torch.equal(d_cf, p_cf) and torch.equal(d_learn, p_learn)
 
 
-@pytest.mark.parametrize("w,k,c", [(4, 7, 12), (8, 60, 16), (16, 300, 16)])
+@pytest.mark.parametrize("w,k,c", [(4, 7, 12), (8, 60, 16), (16, 300, 16), (9, 300, 16), (6, 60, 14)])
 def test_vdre_matches_oracle_and_vate(w, k, c):
     """Distance-recorder counters (the paper's VDRE baseline, full-pool
     maintenance every slice): pool bit-exact with the oracle's DR mode, and
     live counts / estimates identical to a VATE sketch with the same hashing
     (the paper: same mapping => same estimates)."""
     rng = np.random.default_rng(w + k)
-    w_at = 16 if (1 << w) < 2 * k + 1 else w
+    w_at = (2 * k).bit_length() if (1 << w) < 2 * k + 1 else w   # exact ATs where the DR width is too small
     dr = Config(c, w, k, 64, seed_a=7, seed_b=8, counter=1)
     at = Config(c, w_at, k, 64, seed_a=7, seed_b=8, counter=0)
     gdr, gat = Sketch(dr), Sketch(at)

@@ -341,11 +341,12 @@ def test_state_machine_and_clock():
         OracleSketch(2, 8, 3, 16)                            # 2^c < 2k
 
 
-@pytest.mark.parametrize("w", [4, 8, 16])
+@pytest.mark.parametrize("w", [4, 8, 16, 2, 3, 7, 10, 13])
 def test_packed_layout(w):
-    """Container layout: AT p occupies bits [p*w, (p+1)*w) of a little-endian
-    byte stream.  Unpacked here bit by bit with numpy."""
-    k = 3 if w == 4 else 60 if w == 8 else 300
+    """Pool layout: AT p occupies bits [p*w, (p+1)*w) of a little-endian bit
+    stream, for the 4/8/16-bit containers and for exact widths (the paper's
+    ceil(log2(2k+1))-bit ATs).  Unpacked here bit by bit with numpy."""
+    k = {4: 3, 8: 60, 16: 300}.get(w, min((2**w - 1) // 2, 400))
     s = OracleSketch(10, w, k, 8)
     rng = np.random.default_rng(w)
     vals = rng.integers(0, 2 * k + 1, size=s.N).astype(np.uint16)
