@@ -674,6 +674,7 @@ struct vate_sketch {
     uint64_t max_block_chunks;   // chunks a due block can overlap
     int closed;                  // 1: slice ended, estimates allowed
     int dead;                    // sticky device error
+    uint32_t lds_budget;         // dynamic LDS a partitioned-scatter workgroup may use (bytes)
     char err[256];
 };
 
@@ -844,8 +845,8 @@ static bool part_geo(const vate_sketch *s, uint64_t n, PartGeo *out)
     p.rowp = (G.k + 2u) / 2u;
     p.dbytes = G.k < 255 ? 1u : 2u;
     // Hosts per subgroup: the largest count whose VATs fit the scatter's
-    // registers, whose padded sorted entries (+ 16-bit slice counters, keys)
-    // fit its LDS, and whose histograms fit the finalize's LDS.
+    // registers, whose padded sorted entries (+ slice counters, keys) fit its
+    // LDS, and whose histograms fit the finalize's LDS.
     const uint64_t nsp = (((ns + 1) >> 1) + 3) & ~3ull;
     auto lds_for = [&](uint64_t hosts) {
         const uint64_t cap = (hosts * G.g + 3 * ns + 3) & ~3ull;
@@ -854,7 +855,7 @@ static bool part_geo(const vate_sketch *s, uint64_t n, PartGeo *out)
     uint64_t hosts = kRunMaxHosts;
     hosts = std::min<uint64_t>(hosts, kRunMaxEntries / G.g);
     hosts = std::min<uint64_t>(hosts, kFinHistBytes / (4ull * p.rowp));
-    while (hosts > 0 && lds_for(hosts) > kRunLdsBudget) --hosts;
+    while (hosts > 0 && lds_for(hosts) > s->lds_budget) --hosts;
     if (hosts == 0) return false;
     p.hosts = (uint32_t)hosts;
     p.n_sub = (uint32_t)((n + hosts - 1) / hosts);
@@ -916,7 +917,7 @@ static int launch_part_typed(vate_sketch *s, const PartGeo &pg, const RunWs &w, 
 {
     static bool attr = false;
     if (!attr) {
-        int rc = set_lds_limit(s, reinterpret_cast<const void *>(&k_run_scatter), kRunLdsBudget);
+        int rc = set_lds_limit(s, reinterpret_cast<const void *>(&k_run_scatter), s->lds_budget);
         if (rc == VATE_OK)
             rc = set_lds_limit(s, reinterpret_cast<const void *>(&k_run_lookup<W, DT>), 1u << kSliceBytesLog2);
         if (rc == VATE_OK)
@@ -1000,6 +1001,17 @@ int vate_create(const vate_params *p, void *pool_dev, void *state_dev, void *str
     const bool exact = p->width != 4 && p->width != 8 && p->width != 16;
     const uint64_t E = exact ? 32 : 128 / p->width;      // counters per word group / 16-byte chunk
     s->max_block_chunks = (maxb + E - 1) / E + 1;
+    {   // LDS a workgroup may use: the largest the device reports (gfx950: 160 KiB)
+        int dev = 0, lds = 64 * 1024;
+        if (hipGetDevice(&dev) == hipSuccess)
+            for (hipDeviceAttribute_t a : {hipDeviceAttributeMaxSharedMemoryPerBlock,
+                                           hipDeviceAttributeSharedMemPerBlockOptin,
+                                           hipDeviceAttributeMaxSharedMemoryPerMultiprocessor}) {
+                int v = 0;
+                if (hipDeviceGetAttribute(&v, a, dev) == hipSuccess && v > lds) lds = v;
+            }
+        s->lds_budget = std::min<uint32_t>((uint32_t)lds, kRunLdsMax) - kRunLdsStatic;
+    }
     s->closed = 0;
     s->dead = 0;
     s->err[0] = 0;

@@ -33,7 +33,8 @@
 constexpr uint32_t kRunThreads = 1024;                          // scatter / lookup workgroup
 constexpr uint32_t kRunPerThread = 32;                          // VATs hashed per scatter thread
 constexpr uint32_t kRunMaxEntries = kRunThreads * kRunPerThread; // VATs per subgroup
-constexpr uint32_t kRunLdsBudget = 152u * 1024u;                // scatter LDS ceiling (bytes)
+constexpr uint32_t kRunLdsMax = 160u * 1024u;                   // gfx950 LDS per workgroup
+constexpr uint32_t kRunLdsStatic = 64u;                         // k_run_scatter's static LDS (wsum)
 constexpr uint32_t kSliceBytesLog2 = 17;                        // pool bytes per slice: 128 KiB
 constexpr uint32_t kRunMaxSlices = 8192;                        // pools up to 1 GiB
 constexpr uint32_t kRunMaxHosts = 1024;                         // hosts per subgroup
@@ -83,25 +84,41 @@ __global__ void __launch_bounds__(kRunThreads) k_run_scatter(Geo G, PartGeo PG, 
     for (uint32_t h = t; h < nh; h += kRunThreads) keys[h] = host_key(G, hosts[h0 + h]);
     __syncthreads();
 
-    // VAT v = t + j * kRunThreads is VAT i = v mod g of host v / g.
-    const uint32_t sl = PG.sl, mask = (1u << sl) - 1u;
+    // VAT v = t + j * kRunThreads is VAT i = v mod g of host v / g.  H's
+    // multiplier i * phi is carried along (mod 2^32); when g divides the
+    // workgroup size, i (and i * phi) stay fixed and only the host advances.
+    // Iterations j < jfull are full for every thread (a uniform branch); the
+    // ragged tail is iteration jfull.  H(aip, i) = top c bits of the mix
+    // (shift = 32 - c is at most 31).
+    const uint32_t mask = (1u << PG.sl) - 1u;
     const uint32_t host_t = t / G.g, i_t = t - host_t * G.g;
+    const uint32_t jfull = nv / kRunThreads, tail = nv - jfull * kRunThreads;
+    const uint32_t d_ik = PG.dr * kPhi, g_ik = G.g * kPhi;
     uint32_t pid[kRunPerThread];
-    {
-        uint32_t host = host_t, i = i_t;
+    if (PG.dr == 0) {
+        const uint32_t ik = i_t * kPhi;
 #pragma unroll
         for (uint32_t j = 0; j < kRunPerThread; ++j) {
-            if (t + j * kRunThreads < nv) {
-                pid[j] = vat_pid(G, keys[host], i);
-                const uint32_t b = pid[j] >> sl;
+            const uint32_t host = host_t + j * PG.dq;
+            if (j < jfull || (j == jfull && t < tail)) {
+                pid[j] = mix(keys[host] ^ ik) >> G.shift;
+                const uint32_t b = pid[j] >> PG.sl;
                 atomicAdd(&cnt[b >> 1], 1u << ((b & 1u) << 4));
             }
-            i += PG.dr;
-            host += PG.dq;
-            if (i >= G.g) {
-                i -= G.g;
-                ++host;
+        }
+    } else {
+        uint32_t host = host_t, i = i_t, ik = i_t * kPhi;
+#pragma unroll
+        for (uint32_t j = 0; j < kRunPerThread; ++j) {
+            if (j < jfull || (j == jfull && t < tail)) {
+                pid[j] = mix(keys[host] ^ ik) >> G.shift;
+                const uint32_t b = pid[j] >> PG.sl;
+                atomicAdd(&cnt[b >> 1], 1u << ((b & 1u) << 4));
             }
+            const bool wrap = i + PG.dr >= G.g;
+            i = i + PG.dr - (wrap ? G.g : 0u);
+            ik = ik + d_ik - (wrap ? g_ik : 0u);
+            host += PG.dq + (wrap ? 1u : 0u);
         }
     }
     __syncthreads();
@@ -136,31 +153,36 @@ __global__ void __launch_bounds__(kRunThreads) k_run_scatter(Geo G, PartGeo PG, 
         cnt[w] = p0 | (p1 << 16);
         for (uint32_t x = p0 + c0; x < p1; ++x) sorted[x] = kRunPad;
         for (uint32_t x = p1 + c1; x < run; ++x) sorted[x] = kRunPad;
-        const uint32_t b = 2u * w;
-        table[((size_t)(b / PG.sub) * PG.n_sub + s) * PG.sub + b % PG.sub] = (uint16_t)p0;
-        if (b + 1 < PG.n_slices)
-            table[((size_t)((b + 1) / PG.sub) * PG.n_sub + s) * PG.sub + (b + 1) % PG.sub] = (uint16_t)p1;
     }
     uint32_t total = 0;
     for (uint32_t q = 0; q < kRunThreads / 64; ++q) total += wsum[q];
+    __syncthreads();
+    // Run starts to the table, one (super-slice, subgroup) cell per store:
+    // the cursor words are the starts as little-endian u16, slice by slice.
+    if (PG.sub == kSuper) {
+        for (uint32_t B = t; B < PG.n_super; B += kRunThreads)
+            reinterpret_cast<uint4 *>(table)[(size_t)B * PG.n_sub + s] = reinterpret_cast<const uint4 *>(cnt)[B];
+    } else {
+        const uint16_t *starts = reinterpret_cast<const uint16_t *>(cnt);
+        for (uint32_t b = t; b < PG.n_slices; b += kRunThreads)
+            table[((size_t)(b / PG.sub) * PG.n_sub + s) * PG.sub + b % PG.sub] = starts[b];
+    }
     if (t == 0) table[((size_t)PG.n_super * PG.n_sub + s) * PG.sub] = (uint16_t)total;
     __syncthreads();
 
     {
+        auto place = [&](uint32_t p, uint32_t host) {
+            const uint32_t b = p >> PG.sl, sh16 = (b & 1u) << 4;
+            const uint32_t slot = (atomicAdd(&cnt[b >> 1], 1u << sh16) >> sh16) & 0xFFFFu;
+            sorted[slot] = (host << PG.sl) | (p & mask);
+        };
         uint32_t host = host_t, i = i_t;
 #pragma unroll
         for (uint32_t j = 0; j < kRunPerThread; ++j) {
-            if (t + j * kRunThreads < nv) {
-                const uint32_t b = pid[j] >> sl, sh16 = (b & 1u) << 4;
-                const uint32_t slot = (atomicAdd(&cnt[b >> 1], 1u << sh16) >> sh16) & 0xFFFFu;
-                sorted[slot] = (host << sl) | (pid[j] & mask);
-            }
-            i += PG.dr;
-            host += PG.dq;
-            if (i >= G.g) {
-                i -= G.g;
-                ++host;
-            }
+            if (j < jfull || (j == jfull && t < tail)) place(pid[j], host);
+            const bool wrap = i + PG.dr >= G.g;
+            i = i + PG.dr - (wrap ? G.g : 0u);
+            host += PG.dq + (wrap ? 1u : 0u);
         }
     }
     __syncthreads();
