@@ -843,7 +843,8 @@ static bool part_geo(const vate_sketch *s, uint64_t n, PartGeo *out)
     p.n_super = p.n_slices / p.sub;
     p.xcd = p.n_super >= 8 ? 1u : 0u;
     p.rowp = (G.k + 2u) / 2u;
-    p.dbytes = G.k < 255 ? 1u : 2u;
+    p.dbits = 1;                                        // distances 0..k and an all-ones padding mark
+    while ((1u << p.dbits) - 1u <= G.k) ++p.dbits;
     // Hosts per subgroup: the largest count whose VATs fit the scatter's
     // registers, whose padded sorted entries (+ slice counters, keys) fit its
     // LDS, and whose histograms fit the finalize's LDS.
@@ -855,6 +856,7 @@ static bool part_geo(const vate_sketch *s, uint64_t n, PartGeo *out)
     uint64_t hosts = kRunMaxHosts;
     hosts = std::min<uint64_t>(hosts, kRunMaxEntries / G.g);
     hosts = std::min<uint64_t>(hosts, kFinHistBytes / (4ull * p.rowp));
+    hosts = std::min<uint64_t>(hosts, 1ull << (16 - p.dbits));   // host and distance share a 16-bit result
     while (hosts > 0 && lds_for(hosts) > s->lds_budget) --hosts;
     if (hosts == 0) return false;
     p.hosts = (uint32_t)hosts;
@@ -876,7 +878,7 @@ static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 struct RunWs {
     uint32_t *entries;          // [n_sub][region] sorted entries
-    void *dist;                 // [n_sub][region] distances (u8 or u16)
+    uint16_t *res;              // [n_sub][region] lookup results: host within subgroup, distance
     uint16_t *table;            // [n_super + 1][n_sub][sub] run starts
     unsigned long long *cum;    // [k + 1] census prefix (several windows)
     uint32_t *rows;             // [n_sub 2^sh][rowp] packed histograms (learned estimate)
@@ -891,8 +893,8 @@ static RunWs run_ws(const PartGeo &pg, uint32_t k, void *base, bool learned = fa
     size_t off = 0;
     w.entries = reinterpret_cast<uint32_t *>(p + off);
     off += align256(ents * 4);
-    w.dist = reinterpret_cast<void *>(p + off);
-    off += align256(ents * pg.dbytes);
+    w.res = reinterpret_cast<uint16_t *>(p + off);
+    off += align256(ents * 2);
     w.table = reinterpret_cast<uint16_t *>(p + off);
     off += align256((size_t)(pg.n_super + 1) * pg.n_sub * pg.sub * 2);
     w.cum = reinterpret_cast<unsigned long long *>(p + off);
@@ -910,44 +912,33 @@ static int set_lds_limit(vate_sketch *s, const void *fn, uint32_t bytes)
     return VATE_OK;
 }
 
-template <int W, typename DT, int MODE>
-static int launch_part_typed(vate_sketch *s, const PartGeo &pg, const RunWs &w, const uint32_t *hosts, uint32_t n,
-                             uint32_t kprime, float *est, uint32_t *live, uint32_t *hist, const Windows &win,
-                             const void *weights, float *cf, hipStream_t st)
-{
-    static bool attr = false;
-    if (!attr) {
-        int rc = set_lds_limit(s, reinterpret_cast<const void *>(&k_run_scatter), s->lds_budget);
-        if (rc == VATE_OK)
-            rc = set_lds_limit(s, reinterpret_cast<const void *>(&k_run_lookup<W, DT>), 1u << kSliceBytesLog2);
-        if (rc == VATE_OK)
-            rc = set_lds_limit(s, reinterpret_cast<const void *>(&k_run_finalize<DT, MODE>), kFinHistBytes);
-        if (rc != VATE_OK) return rc;
-        attr = true;
-    }
-    DT *dist = static_cast<DT *>(w.dist);
-    k_run_scatter<<<pg.n_sub, kRunThreads, pg.lds_scatter, st>>>(s->G, pg, hosts, n, w.entries, w.table);
-    k_run_lookup<W, DT><<<pg.n_slices, kRunThreads, pg.lds_lookup, st>>>(s->G, pg, s->pool, s->st, w.entries,
-                                                                          w.table, dist);
-    if (MODE == kFinMulti) k_census_prefix<<<1, 64, 0, st>>>(s->G, s->st, w.cum);
-    k_run_finalize<DT, MODE><<<pg.n_sub, kFinThreads, pg.lds_final, st>>>(
-        s->G, pg, s->st, n, kprime, w.entries, dist, w.table, est, live, MODE == kFinLearned ? w.rows : hist, win, w.cum,
-        static_cast<const mlp::Packed *>(weights), cf);
-    if (MODE == kFinLearned)
-        k_learned_rows<<<(n + 63) / 64, 256, 0, st>>>(s->G, s->st, n, pg.rowp, w.rows, cf,
-                                                       static_cast<const mlp::Packed *>(weights), est);
-    return VATE_OK;
-}
-
 template <int W, int MODE>
 static int launch_part(vate_sketch *s, const PartGeo &pg, void *ws, const uint32_t *hosts, uint32_t n,
                        uint32_t kprime, float *est, uint32_t *live, uint32_t *hist, const Windows &win,
                        const void *weights, float *cf, hipStream_t st)
 {
+    static bool attr = false;
+    if (!attr) {
+        int rc = set_lds_limit(s, reinterpret_cast<const void *>(&k_run_scatter), s->lds_budget);
+        if (rc == VATE_OK)
+            rc = set_lds_limit(s, reinterpret_cast<const void *>(&k_run_lookup<W>), 1u << kSliceBytesLog2);
+        if (rc == VATE_OK)
+            rc = set_lds_limit(s, reinterpret_cast<const void *>(&k_run_finalize<MODE>), kFinHistBytes);
+        if (rc != VATE_OK) return rc;
+        attr = true;
+    }
     const RunWs w = run_ws(pg, s->p.k, ws, MODE == kFinLearned);
-    if (pg.dbytes == 1)
-        return launch_part_typed<W, uint8_t, MODE>(s, pg, w, hosts, n, kprime, est, live, hist, win, weights, cf, st);
-    return launch_part_typed<W, uint16_t, MODE>(s, pg, w, hosts, n, kprime, est, live, hist, win, weights, cf, st);
+    k_run_scatter<<<pg.n_sub, kRunThreads, pg.lds_scatter, st>>>(s->G, pg, hosts, n, w.entries, w.table);
+    k_run_lookup<W><<<pg.n_slices, kRunThreads, pg.lds_lookup, st>>>(s->G, pg, s->pool, s->st, w.entries, w.table,
+                                                                       w.res);
+    if (MODE == kFinMulti) k_census_prefix<<<1, 64, 0, st>>>(s->G, s->st, w.cum);
+    k_run_finalize<MODE><<<pg.n_sub, kFinThreads, pg.lds_final, st>>>(
+        s->G, pg, s->st, n, kprime, w.res, w.table, est, live, MODE == kFinLearned ? w.rows : hist, win, w.cum,
+        static_cast<const mlp::Packed *>(weights), cf);
+    if (MODE == kFinLearned)
+        k_learned_rows<<<(n + 63) / 64, 256, 0, st>>>(s->G, s->st, n, pg.rowp, w.rows, cf,
+                                                       static_cast<const mlp::Packed *>(weights), est);
+    return VATE_OK;
 }
 
 template <int MODE>

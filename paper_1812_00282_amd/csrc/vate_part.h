@@ -16,19 +16,19 @@
 //                 slices.  Run starts go to a u16 table laid out
 //                 [super-slice][subgroup][slice in super].
 //  k_run_lookup   one workgroup per pool slice (128 KiB of ATs, held in LDS).
-//                 Walks that slice's run in every subgroup and writes each
-//                 VAT's distance (Eq. 5, CheckAT; k = inactive for window k)
-//                 beside its entry.  The 8 slices of a super-slice are given
+//                 Walks that slice's run in every subgroup and writes, beside
+//                 each entry, a 16-bit result: the host within the subgroup
+//                 and the VAT's distance (Eq. 5, CheckAT; k = inactive for
+//                 window k).  The 8 slices of a super-slice are given
 //                 to one XCD: their runs are adjacent in memory, so the lines
 //                 they read and the distance bytes they write meet in that
 //                 XCD's L2.
-//  k_run_finalize one workgroup per subgroup.  Streams the entries and
-//                 distances back, builds each host's distance histogram in LDS
-//                 and forms Eq. 11 for k', several windows, or the learned
-//                 estimate from it.
+//  k_run_finalize one workgroup per subgroup.  Streams the results back,
+//                 builds each host's distance histogram in LDS and forms
+//                 Eq. 11 for k', several windows, or the learned estimate.
 //
-// HBM traffic per VAT: 4 B entry written and read back twice, 1 B (2 B when
-// k >= 255) distance written and read once.
+// HBM traffic per VAT: 4 B entry written and read back once, 2 B result
+// written and read back once.
 
 constexpr uint32_t kRunThreads = 1024;                          // scatter / lookup workgroup
 constexpr uint32_t kRunPerThread = 32;                          // VATs hashed per scatter thread
@@ -58,7 +58,7 @@ struct PartGeo {
     uint32_t rowp;        // u32 words per packed 16-bit histogram row, ceil((k + 1) / 2)
     uint32_t xcd;         // map the slices of a super-slice to one XCD
     uint32_t lds_scatter, lds_lookup, lds_final;
-    uint32_t dbytes;      // bytes per stored distance: 1 if k < 255, else 2
+    uint32_t dbits;       // distance bits of a result: values 0..k, all ones = padding
 };
 
 // ---------------------------------------------------------------------------
@@ -200,23 +200,12 @@ __device__ __forceinline__ void store4(DT *p, const uint32_t d[4])
         *reinterpret_cast<uint2 *>(p) = make_uint2(d[0] | (d[1] << 16), d[2] | (d[3] << 16));
 }
 
-template <typename DT>
-__device__ __forceinline__ void load4(const DT *p, uint32_t d[4])
-{
-    if constexpr (sizeof(DT) == 1) {
-        const uint32_t v = *reinterpret_cast<const uint32_t *>(p);
-        d[0] = v & 0xFFu, d[1] = (v >> 8) & 0xFFu, d[2] = (v >> 16) & 0xFFu, d[3] = v >> 24;
-    } else {
-        const uint2 v = *reinterpret_cast<const uint2 *>(p);
-        d[0] = v.x & 0xFFFFu, d[1] = v.x >> 16, d[2] = v.y & 0xFFFFu, d[3] = v.y >> 16;
-    }
-}
-
-template <int W, typename DT>
+template <int W>
 __global__ void __launch_bounds__(kRunThreads) k_run_lookup(Geo G, PartGeo PG, const uint8_t *__restrict__ pool,
                                                            const DevState *__restrict__ st,
                                                            const uint32_t *__restrict__ entries,
-                                                           const uint16_t *__restrict__ table, DT *__restrict__ dist)
+                                                           const uint16_t *__restrict__ table,
+                                                           uint16_t *__restrict__ res)
 {
     extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
     const uint8_t *at = reinterpret_cast<const uint8_t *>(lds);
@@ -276,11 +265,14 @@ __global__ void __launch_bounds__(kRunThreads) k_run_lookup(Geo G, PartGeo PG, c
     const uint32_t grp = lane >> 3, gl = lane & 7u;
     const size_t row = (size_t)B * PG.n_sub, next_row = (size_t)(B + 1) * PG.n_sub;
     // Runs start and end on 4-entry boundaries: every chunk belongs to one
-    // run.  Padding entries get a distance too; the finalize skips them.
+    // run.  A padding entry's result is all ones.
     auto resolve = [&](uint32_t s, uint32_t c, const uint4 &e4) {
-        const uint32_t d[4] = {dist_of(e4.x & mask), dist_of(e4.y & mask), dist_of(e4.z & mask),
-                               dist_of(e4.w & mask)};
-        store4<DT>(dist + (size_t)s * PG.region + 4u * c, d);
+        const uint32_t e[4] = {e4.x, e4.y, e4.z, e4.w};
+        uint32_t r[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+            r[m] = e[m] == kRunPad ? 0xFFFFu : (((e[m] >> sl) << PG.dbits) | dist_of(e[m] & mask));
+        store4<uint16_t>(res + (size_t)s * PG.region + 4u * c, r);
     };
     // Software pipeline over groups of 64 subgroups: while group i is
     // resolved, the entries of group i + 1 and the run bounds of group i + 2
@@ -356,11 +348,10 @@ __device__ __forceinline__ uint32_t hist_bin(const uint32_t *row, uint32_t d)
     return (row[d >> 1] >> ((d & 1u) << 4)) & 0xFFFFu;
 }
 
-template <typename DT, int MODE>
+template <int MODE>
 __global__ void __launch_bounds__(kFinThreads) k_run_finalize(Geo G, PartGeo PG, const DevState *__restrict__ st,
                                                              uint32_t n, uint32_t kprime,
-                                                             const uint32_t *__restrict__ entries,
-                                                             const DT *__restrict__ dist,
+                                                             const uint16_t *__restrict__ res,
                                                              const uint16_t *__restrict__ table, float *__restrict__ est,
                                                              uint32_t *__restrict__ live_out,
                                                              uint32_t *__restrict__ hist_out, Windows win,
@@ -377,32 +368,30 @@ __global__ void __launch_bounds__(kFinThreads) k_run_finalize(Geo G, PartGeo PG,
     for (uint32_t q = t; q < nh * rowp; q += kFinThreads) hist[q] = 0;
     __syncthreads();
     {
-        const uint4 *ent = reinterpret_cast<const uint4 *>(entries + (size_t)s * PG.region);
-        const DT *dd = dist + (size_t)s * PG.region;
-        const uint32_t sl = PG.sl;
-        constexpr uint32_t U = 4;     // chunks in flight per thread
-        const uint32_t nch = nvp >> 2;
+        const uint4 *rr = reinterpret_cast<const uint4 *>(res + (size_t)s * PG.region);   // 8 results per load
+        const uint32_t dmask = (1u << PG.dbits) - 1u;
+        constexpr uint32_t U = 4;     // loads in flight per thread
+        const uint32_t nch = (nvp + 7u) >> 3;     // nvp is a multiple of 4
         for (uint32_t c0 = t; c0 < nch; c0 += U * kFinThreads) {
-            uint4 e4[U];
-            uint32_t d[U][4];
+            uint4 r4[U];
 #pragma unroll
             for (uint32_t u = 0; u < U; ++u) {
                 const uint32_t c = c0 + u * kFinThreads;
-                if (c < nch) {
-                    e4[u] = ent[c];
-                    load4<DT>(dd + 4u * c, d[u]);
-                }
+                if (c < nch) r4[u] = rr[c];
             }
 #pragma unroll
             for (uint32_t u = 0; u < U; ++u) {
                 const uint32_t c = c0 + u * kFinThreads;
                 if (c >= nch) break;
-                const uint32_t e[4] = {e4[u].x, e4[u].y, e4[u].z, e4[u].w};
+                const uint32_t w[4] = {r4[u].x, r4[u].y, r4[u].z, r4[u].w};
 #pragma unroll
-                for (int m = 0; m < 4; ++m) {
-                    if (e[m] == kRunPad) continue;
-                    const uint32_t dm = min(d[u][m], G.k);
-                    atomicAdd(&hist[(e[m] >> sl) * rowp + (dm >> 1)], 1u << ((dm & 1u) << 4));
+                for (int m = 0; m < 8; ++m) {
+                    if (8u * c + m >= nvp) break;
+                    const uint32_t r = (w[m >> 1] >> ((m & 1) << 4)) & 0xFFFFu;
+                    const uint32_t d = r & dmask;
+                    if (d == dmask) continue;
+                    const uint32_t dm = min(d, G.k);
+                    atomicAdd(&hist[(r >> PG.dbits) * rowp + (dm >> 1)], 1u << ((dm & 1u) << 4));
                 }
             }
         }
