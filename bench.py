@@ -42,7 +42,7 @@ def kernel_source_hash() -> str:
     import hashlib
 
     h = hashlib.sha256()
-    for f in ("vate.hip", "vate_core.h", "mlp_core.h"):
+    for f in ("vate.hip", "vate_core.h", "vate_part.h", "vate_exact.h", "mlp_core.h"):
         h.update(open(os.path.join(ROOT, "paper_1812_00282_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -171,6 +171,47 @@ def batched_leg(dev, n_slices: int = 8) -> dict:
             "tune": tune}
 
 
+def blocked_leg(dev, slices, hosts, held_independent, block_log2: int = 6, steps: int = 10) -> dict:
+    """The opt-in locality-blocked H (blocks of 2^b consecutive VATs; not the
+    paper's H) on the same 40 Gb/s stream: estimate time for all 1M hosts
+    (closed form, window k: the whole-block popcount gather; with the
+    distance histogram: the per-VAT gather), and the closed form's accuracy on
+    the held-out probe episodes against the independent H."""
+    import torch
+
+    from paper_1812_00282_amd import streams
+    from paper_1812_00282_amd import train as T
+    from paper_1812_00282_amd.sketch import Config, Sketch
+
+    wl = streams.LINK40G
+    cfg = Config(wl.log2_pool, wl.width, wl.k, wl.g, seed_a=0xA5A5, seed_b=0x5A5A, block_log2=block_log2)
+    sk = Sketch(cfg, device=dev)
+    est = torch.empty(hosts.numel(), dtype=torch.float32, device=dev)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    hist = torch.empty((hosts.numel(), wl.k + 1), dtype=torch.int32, device=dev)
+    direct, with_hist = [], []
+    for s in range(4 + steps):
+        sk.ingest(slices[s % len(slices)])
+        sk.close_slice()
+        ev[0].record()
+        sk.estimate(hosts, want_live=False, out=(est, None, None))
+        ev[1].record()
+        sk.estimate(hosts, want_live=False, out=(est, None, hist))
+        ev[2].record()
+        torch.cuda.synchronize()
+        if s >= 4:
+            direct.append(ev[0].elapsed_time(ev[1]))
+            with_hist.append(ev[1].elapsed_time(ev[2]))
+    del sk
+    torch.cuda.empty_cache()
+    bg = T.background(4, dev)
+    held = T.generate(T.HELD_OUT_SEEDS[:2], bg, device=dev, block_log2=block_log2)
+    return {"block_log2": block_log2, "hosts": hosts.numel(),
+            "estimate_ms": float(np.median(direct)), "estimate_ms_with_histogram": float(np.median(with_hist)),
+            "closed_form_rel_error": T.closed_form_error(held),
+            "closed_form_rel_error_independent_h": T.closed_form_error(held_independent)}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -181,6 +222,8 @@ def main() -> int:
                     help="skip the learned vs closed-form comparison on held-out episodes")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched-sketches leg (16 sketches, hipGraph replay)")
+    ap.add_argument("--no-blocked", action="store_true",
+                    help="skip the locality-blocked H leg (opt-in variant, not the paper's H)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device-to-device copy (reference kernel for "
                          "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE readings)")
@@ -316,12 +359,17 @@ def main() -> int:
         "real_time_margin": 1000.0 / ms_per_step,    # 1 s slices (Sec. 5's real-time criterion)
         "roofline": roofline,
     }
+    held = None
     if not args.no_eval:
         log("[bench] learned vs closed form on held-out probe episodes")
         bg = T.background(4, dev)
         held = T.generate(T.HELD_OUT_SEEDS[:2], bg, device=dev)
         line["learned_vs_closed_form"] = {"weights": weights_src,
                                           **T.evaluate(theta, held, device=dev)}
+        del bg
+    if not args.no_blocked and held is not None:
+        log("[bench] locality-blocked H (opt-in variant)")
+        line["blocked_h"] = blocked_leg(dev, slices, hosts, held)
     if not args.no_batch:
         log("[bench] batched sketches")
         del sk

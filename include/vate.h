@@ -76,6 +76,14 @@ typedef struct vate_params {
                             at k, is reset to 0 by a packet and incremented for
                             the whole pool at every slide, Sec. 1; it needs
                             2^width >= k+1).  Same hashing, estimates and ABI. */
+    uint32_t block_log2; /* 0: H as above (the paper's independent VATs).
+                            b in 1..10, b <= c: locality-blocked H, not the
+                            paper's - VAT i of a host is slot i mod 2^b of the
+                            host's block floor(i / 2^b), a run of 2^b
+                            consecutive ATs whose position is the top c - b
+                            bits of mix(mix(aip ^ seed_a) ^ floor(i/2^b) *
+                            0x9E3779B9), times 2^b.  Same ABI; fewer cache
+                            lines per host at a cost in estimator variance. */
 } vate_params;
 
 typedef struct vate_sketch vate_sketch;

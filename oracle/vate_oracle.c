@@ -50,6 +50,8 @@ typedef struct {
     uint32_t c, w, k, g, partition;
     uint32_t counter;      /* 0: asynchronous timestamps (VATE); 1: distance
                               recorders (VDRE, the paper's baseline) */
+    uint32_t blog;         /* 0: H as read from Sec. 4.1 (independent VATs);
+                              b > 0: locality-blocked H, blocks of 2^b VATs */
     uint32_t seed_a, seed_b;
     uint64_t N;            /* 2^c ATs in the pool ATP */
     uint16_t *ATP;         /* AT values in [0, 2k] */
@@ -85,6 +87,20 @@ uint32_t o_hash_H(uint32_t c, uint32_t seed_a, uint32_t aip, uint32_t i)
     return (uint32_t)(((uint64_t)x << c) >> 32);
 }
 
+/* Locality-blocked H (an opt-in variant, not the paper's): VAT i of a host is
+ * slot i mod 2^b of the host's block floor(i / 2^b), and that block sits at a
+ * block-aligned position given by the top c - b bits of the same mix applied
+ * to the block number.  b = 0 is o_hash_H. */
+uint32_t o_hash_H_blocked(uint32_t c, uint32_t b, uint32_t seed_a, uint32_t aip, uint32_t i)
+{
+    if (b == 0)
+        return o_hash_H(c, seed_a, aip, i);
+    uint32_t j = i >> b;
+    uint32_t x = o_fmix32(o_fmix32(aip ^ seed_a) ^ (uint32_t)(j * PHI));
+    uint32_t block = (uint32_t)(((uint64_t)x << (c - b)) >> 32);   /* floor(x * 2^(c-b) / 2^32) */
+    return (block << b) | (i & ((1u << b) - 1u));
+}
+
 uint32_t o_BH(const o_vate *s, uint32_t bip)
 {
     return o_hash_BH(s->g, s->seed_b, bip);
@@ -92,7 +108,7 @@ uint32_t o_BH(const o_vate *s, uint32_t bip)
 
 uint32_t o_H(const o_vate *s, uint32_t aip, uint32_t i)
 {
-    return o_hash_H(s->c, s->seed_a, aip, i);
+    return o_hash_H_blocked(s->c, s->blog, s->seed_a, aip, i);
 }
 
 /* ---- AT blocks (Eq. 6-10, Fig. 4 / Fig. 5) ---- */
@@ -164,9 +180,9 @@ uint32_t o_preserve_fast(uint32_t value, uint32_t act, uint32_t k)
 /* ---- sketch lifecycle ---- */
 
 o_vate *o_create(uint32_t c, uint32_t w, uint32_t k, uint32_t g,
-                 uint32_t seed_a, uint32_t seed_b, uint32_t partition, uint32_t counter)
+                 uint32_t seed_a, uint32_t seed_b, uint32_t partition, uint32_t counter, uint32_t blog)
 {
-    if (c < 1 || c > 32 || k < 1 || g < 1 || counter > 1)
+    if (c < 1 || c > 32 || k < 1 || g < 1 || counter > 1 || blog > 10 || blog > c)
         return NULL;
     if (w < 1 || w > 16)
         return NULL;
@@ -183,6 +199,7 @@ o_vate *o_create(uint32_t c, uint32_t w, uint32_t k, uint32_t g,
         return NULL;
     s->c = c; s->w = w; s->k = k; s->g = g; s->partition = partition;
     s->counter = counter;
+    s->blog = blog;
     s->seed_a = seed_a; s->seed_b = seed_b;
     s->N = 1ull << c;
     s->ATP = (uint16_t *)malloc(s->N * sizeof(uint16_t));

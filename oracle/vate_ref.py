@@ -42,6 +42,7 @@ def lib():
             "o_fmix32": (_u32, [_u32]),
             "o_hash_BH": (_u32, [_u32, _u32, _u32]),
             "o_hash_H": (_u32, [_u32, _u32, _u32, _u32]),
+            "o_hash_H_blocked": (_u32, [_u32, _u32, _u32, _u32, _u32]),
             "o_BH": (_u32, [_vp, _u32]),
             "o_H": (_u32, [_vp, _u32, _u32]),
             "o_block_of": (_u32, [_vp, _u64]),
@@ -50,7 +51,7 @@ def lib():
             "o_checkAT": (_i32, [_u32, _u32, _u32, _u32]),
             "o_preserve_general": (_u32, [_u32, _u32, _u32]),
             "o_preserve_fast": (_u32, [_u32, _u32, _u32]),
-            "o_create": (_vp, [_u32, _u32, _u32, _u32, _u32, _u32, _u32, _u32]),
+            "o_create": (_vp, [_u32, _u32, _u32, _u32, _u32, _u32, _u32, _u32, _u32]),
             "o_checkDR": (_i32, [_u32, _u32]),
             "o_destroy": (None, [_vp]),
             "o_ingest": (None, [_vp, _vp, _u64]),
@@ -93,6 +94,10 @@ def hash_H(c: int, seed_a: int, aip: int, i: int) -> int:
     return lib().o_hash_H(c, seed_a & 0xFFFFFFFF, aip & 0xFFFFFFFF, i)
 
 
+def hash_H_blocked(c: int, b: int, seed_a: int, aip: int, i: int) -> int:
+    return lib().o_hash_H_blocked(c, b, seed_a & 0xFFFFFFFF, aip & 0xFFFFFFFF, i)
+
+
 def check_at(value: int, act: int, k: int, kprime: int) -> bool:
     return bool(lib().o_checkAT(value, act, k, kprime))
 
@@ -113,13 +118,15 @@ class OracleSketch:
     """One VATE sketch on the CPU; same call sequence as the C-ABI library."""
 
     def __init__(self, log2_pool: int, width: int, k: int, g: int,
-                 seed_a: int = 0, seed_b: int = 0, partition: int = 0, counter: int = 0):
+                 seed_a: int = 0, seed_b: int = 0, partition: int = 0, counter: int = 0,
+                 block_log2: int = 0):
         """counter 0: asynchronous timestamps (VATE); 1: distance recorders
-        (VDRE, full-pool maintenance every slice)."""
+        (VDRE, full-pool maintenance every slice).  block_log2 > 0 selects
+        the locality-blocked H (blocks of 2^block_log2 consecutive VATs)."""
         self.c, self.w, self.k, self.g = log2_pool, width, k, g
-        self.partition, self.counter = partition, counter
+        self.partition, self.counter, self.block_log2 = partition, counter, block_log2
         self._s = lib().o_create(log2_pool, width, k, g, seed_a & 0xFFFFFFFF,
-                                 seed_b & 0xFFFFFFFF, partition, counter)
+                                 seed_b & 0xFFFFFFFF, partition, counter, block_log2)
         if not self._s:
             raise ValueError("invalid oracle sketch parameters")
         self.N = lib().o_N(self._s)

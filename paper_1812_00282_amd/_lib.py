@@ -30,6 +30,7 @@ class VateParams(ctypes.Structure):
         ("seed_a", ctypes.c_uint32),
         ("seed_b", ctypes.c_uint32),
         ("counter", ctypes.c_uint32),
+        ("block_log2", ctypes.c_uint32),
     ]
 
 

@@ -84,6 +84,10 @@ int make_geo(const vate_params *p, Geo *G, const char **why)
     }
     if (p->g < 1 || p->g > 65535) { *why = "g must be in [1, 65535]"; return VATE_E_INVAL; }
     if (p->partition > 1) { *why = "partition must be 0 or 1"; return VATE_E_INVAL; }
+    if (p->block_log2 > 10 || p->block_log2 > p->log2_pool) {
+        *why = "block_log2 must be in [0, min(10, log2_pool)]";
+        return VATE_E_INVAL;
+    }
     uint64_t N = 1ull << p->log2_pool;
     if (N < 2ull * p->k) { *why = "pool smaller than 2k ATs"; return VATE_E_INVAL; }
     const bool exact = p->width != 4 && p->width != 8 && p->width != 16;
@@ -101,6 +105,7 @@ int make_geo(const vate_params *p, Geo *G, const char **why)
     g.partition = p->partition;
     g.dr = p->counter;
     g.wb = p->width;
+    g.blog = p->block_log2;
     const uint64_t E = exact ? 32 : 128 / p->width;   // counters per 16-byte chunk / per word group
     if (p->partition == 0) {
         g.a = N / (g.twok - 1);
@@ -459,6 +464,53 @@ __global__ void __launch_bounds__(256) k_estimate(Geo G, const uint8_t *__restri
 }
 
 // ---------------------------------------------------------------------------
+// k_estimate_blocked: the closed form for window k under the locality-blocked
+// H with blocks of >= 32 VATs, where a block is whole 32-bit words of the
+// activity bitmap.  L lanes per host (L = blocks per host rounded up to a
+// power of two, at most 64), each counting the set bits of its blocks with
+// popcount; the host's lanes are summed by shuffles.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_estimate_blocked(Geo G, const DevState *__restrict__ st,
+                                                          const uint32_t *__restrict__ bitmap,
+                                                          const uint32_t *__restrict__ hosts, uint32_t n,
+                                                          uint32_t lanes_log2, float *__restrict__ est,
+                                                          uint32_t *__restrict__ live_out)
+{
+    const uint64_t active_pool = pool_active(st, G.k);
+    const uint32_t L = 1u << lanes_log2;
+    const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t h = gid >> lanes_log2, sub = gid & (L - 1u);
+    const bool valid = h < n;
+    const uint32_t key = host_key(G, valid ? hosts[h] : 0u);
+    const uint32_t beta = 1u << G.blog, words = beta >> 5;
+    const uint32_t nb = (G.g + beta - 1u) >> G.blog;
+    uint32_t live = 0;
+    if (valid)
+        for (uint32_t q = sub; q < nb; q += L) {
+            const uint32_t base = vat_pid(G, key, q << G.blog);          // block-aligned first AT
+            const uint32_t in_block = min(beta, G.g - (q << G.blog));      // VATs of this block
+            const uint32_t *w = bitmap + (base >> 5);
+            for (uint32_t x = 0; x < words; ++x) {
+                const uint32_t lo = x << 5;
+                if (lo >= in_block) break;
+                uint32_t v = w[x];
+                if (in_block - lo < 32) v &= (1u << (in_block - lo)) - 1u;
+                live += __popc(v);
+            }
+        }
+    for (uint32_t off = 1; off < L; off <<= 1) live += __shfl_xor(live, off, 64);
+    if (valid && sub == 0) {
+        est[h] = estimate_from_counts(G.g - live, G.N - active_pool, G.g, G.c);
+        if (live_out) live_out[h] = live;
+    }
+}
+
+static bool blocked_gather_ok(const Geo &G, uint32_t kprime, const uint32_t *hist)
+{
+    return G.blog >= 5 && kprime == G.k && hist == nullptr;
+}
+
+// ---------------------------------------------------------------------------
 // k_estimate_learned: the gather of k_estimate (histogram path, window k)
 // followed, in the same workgroup, by the learned estimator on the matrix
 // cores.  Each wavefront's 64 hosts are fed to the network as four 16-row
@@ -801,6 +853,14 @@ template <int W>
 static void launch_estimate(vate_sketch *s, const uint32_t *hosts, uint32_t n, uint32_t kprime, float *est,
                             uint32_t *live, uint32_t *hist, hipStream_t st)
 {
+    if (blocked_gather_ok(s->G, kprime, hist)) {
+        const uint32_t nb = (s->G.g + (1u << s->G.blog) - 1u) >> s->G.blog;
+        uint32_t lg = 0;
+        while ((1u << lg) < nb && lg < 6) ++lg;
+        k_estimate_blocked<<<grid_for((uint64_t)n << lg, 256, 1u << 30), 256, 0, st>>>(
+            s->G, s->st, reinterpret_cast<const uint32_t *>(s->bitmap), hosts, n, lg, est, live);
+        return;
+    }
     if (hist) {
         const uint32_t k = s->G.k;
         const unsigned threads = k <= 64 ? 256 : k <= 128 ? 128 : 64;
@@ -825,10 +885,12 @@ static void launch_estimate_learned(vate_sketch *s, const uint32_t *hosts, uint3
 // ---- partitioned estimate: geometry, workspace layout and launches ----
 // part_geo returns false when the sketch or host count is outside the
 // partitioned path's limits (a pool above 1 GiB, or g VATs of one host too
-// many for one LDS sort); the entry points then use the direct gather.
+// many for one LDS sort) or the sketch uses the locality-blocked H; the entry
+// points then use the direct gather.
 static bool part_geo(const vate_sketch *s, uint64_t n, PartGeo *out)
 {
     const Geo &G = s->G;
+    if (G.blog > 0) return false;   // blocked VATs: the direct gather already reads whole blocks
     const uint32_t w = s->p.width;
     uint32_t wlog = 0;                                  // ceil(log2 w)
     while ((1u << wlog) < w) ++wlog;

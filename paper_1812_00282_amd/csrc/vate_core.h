@@ -78,6 +78,7 @@ struct Geo {
     uint32_t partition;  // 0: Eq. 9-10, 1: Fig. 5
     uint32_t dr;         // 0: asynchronous timestamps; 1: distance recorders (VDRE)
     uint32_t wb;         // counter width in bits
+    uint32_t blog;       // 0: independent VATs; b > 0: locality-blocked H (blocks of 2^b VATs)
     uint32_t base1;      // Fig. 5: index of the first (a'+1)-sized block, 2k - b'
     uint32_t fast_blocks;// every block but the last holds >= one 16-byte chunk
     Div32 div_a;         // divide by a (Eq. 9) or a' (Fig. 5)
@@ -99,8 +100,15 @@ __host__ __device__ __forceinline__ uint32_t host_key(const Geo &G, uint32_t aip
 // H(aip, i) = top c bits of mix(host_key ^ i * phi).
 __host__ __device__ __forceinline__ uint32_t vat_pid(const Geo &G, uint32_t key, uint32_t i)
 {
-    uint32_t x = mix(key ^ (i * kPhi));
-    return G.shift >= 32 ? 0u : (x >> G.shift);
+    if (G.blog == 0) {
+        const uint32_t x = mix(key ^ (i * kPhi));
+        return x >> G.shift;                     // shift = 32 - c <= 31
+    }
+    // blocked: slot i mod 2^b of the block floor(i / 2^b), placed at the top
+    // c - b bits of the block number's mix, times 2^b
+    const uint32_t bm = (1u << G.blog) - 1u;
+    const uint32_t x = mix(key ^ ((i >> G.blog) * kPhi));
+    return ((x >> G.shift) & ~bm) | (i & bm);
 }
 
 // Block index of an AT (Eq. 9-10 with the last block taking the remainder,

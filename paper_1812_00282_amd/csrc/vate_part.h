@@ -95,7 +95,7 @@ __global__ void __launch_bounds__(kRunThreads) k_run_scatter(Geo G, PartGeo PG, 
     const uint32_t jfull = nv / kRunThreads, tail = nv - jfull * kRunThreads;
     const uint32_t d_ik = PG.dr * kPhi, g_ik = G.g * kPhi;
     uint32_t pid[kRunPerThread];
-    if (PG.dr == 0) {
+    if (PG.dr == 0 && G.blog == 0) {
         const uint32_t ik = i_t * kPhi;
 #pragma unroll
         for (uint32_t j = 0; j < kRunPerThread; ++j) {
@@ -106,12 +106,23 @@ __global__ void __launch_bounds__(kRunThreads) k_run_scatter(Geo G, PartGeo PG, 
                 atomicAdd(&cnt[b >> 1], 1u << ((b & 1u) << 4));
             }
         }
+    } else if (PG.dr == 0) {                 // locality-blocked H, i fixed
+        const uint32_t bm = (1u << G.blog) - 1u, ikb = (i_t >> G.blog) * kPhi, low = i_t & bm;
+#pragma unroll
+        for (uint32_t j = 0; j < kRunPerThread; ++j) {
+            const uint32_t host = host_t + j * PG.dq;
+            if (j < jfull || (j == jfull && t < tail)) {
+                pid[j] = ((mix(keys[host] ^ ikb) >> G.shift) & ~bm) | low;
+                const uint32_t b = pid[j] >> PG.sl;
+                atomicAdd(&cnt[b >> 1], 1u << ((b & 1u) << 4));
+            }
+        }
     } else {
         uint32_t host = host_t, i = i_t, ik = i_t * kPhi;
 #pragma unroll
         for (uint32_t j = 0; j < kRunPerThread; ++j) {
             if (j < jfull || (j == jfull && t < tail)) {
-                pid[j] = mix(keys[host] ^ ik) >> G.shift;
+                pid[j] = G.blog ? vat_pid(G, keys[host], i) : mix(keys[host] ^ ik) >> G.shift;
                 const uint32_t b = pid[j] >> PG.sl;
                 atomicAdd(&cnt[b >> 1], 1u << ((b & 1u) << 4));
             }

@@ -40,10 +40,12 @@ class Config:
     seed_a: int = 0
     seed_b: int = 0
     counter: int = 0      # 0: asynchronous timestamps (VATE); 1: distance recorders (VDRE)
+    block_log2: int = 0   # 0: independent VATs (the paper's H); b > 0: locality-blocked H
 
     def params(self) -> VateParams:
         return VateParams(self.log2_pool, self.width, self.k, self.g, self.partition,
-                          self.seed_a & 0xFFFFFFFF, self.seed_b & 0xFFFFFFFF, self.counter)
+                          self.seed_a & 0xFFFFFFFF, self.seed_b & 0xFFFFFFFF, self.counter,
+                          self.block_log2)
 
 
 def state_bytes(cfg: Config) -> tuple[int, int]:

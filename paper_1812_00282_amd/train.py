@@ -61,8 +61,8 @@ def background(n_slices: int, device) -> list[torch.Tensor]:
 
 
 def generate(seeds, bg, k=60, g=1024, log2_pool=28, n_slices=100, t0=8, device="cuda",
-             probes_range=(64, 512), bg_range=(0.2, 1.0)) -> StateSet:
-    cfg = Config(log2_pool, 8, k, g, seed_a=0x1EA7, seed_b=0x2EA7)
+             probes_range=(64, 512), bg_range=(0.2, 1.0), block_log2=0) -> StateSet:
+    cfg = Config(log2_pool, 8, k, g, seed_a=0x1EA7, seed_b=0x2EA7, block_log2=block_log2)
     xs, rs, ys, cfs, trs = [], [], [], [], []
     for seed in seeds:
         rng = np.random.default_rng(seed)
@@ -138,6 +138,19 @@ def train(data: StateSet, epochs=6, batch=4096, lr=2e-3, seed=0, device="cuda", 
             log(f"[train] epoch {ep} loss(last minibatch) {acc:.4f}")
     torch.cuda.synchronize()
     return theta, history
+
+
+def closed_form_error(data: StateSet) -> dict:
+    """Mean relative error of the closed form (clamped at 1), overall and by
+    truth bucket."""
+    tr = data.truth.double()
+    cf = torch.clamp(data.cf.double(), min=1.0)
+    err = torch.abs(cf - tr) / tr
+    out = {"all": float(err.mean().item())}
+    for lo, hi in BUCKETS:
+        sel = (tr >= lo) & (tr < hi)
+        out[f"[{lo},{hi})"] = float(err[sel].mean().item()) if sel.any() else None
+    return out
 
 
 def evaluate(theta: torch.Tensor, data: StateSet, device="cuda") -> dict:

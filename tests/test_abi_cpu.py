@@ -119,6 +119,24 @@ def test_host_h_matches_oracle(c):
             assert host_hash(cfg, 1, int(aip), i) == vate_ref.hash_H(c, 0x77, int(aip), i)
 
 
+@pytest.mark.parametrize("c,b", [(5, 1), (16, 3), (28, 6), (32, 10), (10, 10)])
+def test_host_h_blocked_matches_oracle(c, b):
+    """The locality-blocked H of the library equals the oracle's."""
+    cfg = Config(c, 16, 4, 64, seed_a=0x51, seed_b=0x99, block_log2=b)
+    rng = np.random.default_rng(c + b)
+    for aip in list(rng.integers(0, 2**32, size=40)) + [0, 2**32 - 1]:
+        for i in (0, 1, 2, 63, 64, 1000, 65534):
+            assert host_hash(cfg, 1, int(aip), i) == vate_ref.hash_H_blocked(c, b, 0x51, int(aip), i)
+
+
+def test_block_log2_validated():
+    for bad in (dict(block_log2=11), dict(log2_pool=5, block_log2=6)):
+        base = dict(log2_pool=16, width=8, k=4, g=128)
+        base.update(bad)
+        with pytest.raises(_lib.VateError):
+            state_bytes(Config(**base))
+
+
 @pytest.mark.parametrize("partition", [0, 1])
 @pytest.mark.parametrize("c,k", [(6, 1), (6, 2), (7, 3), (8, 9), (10, 16), (16, 4),
                                  (16, 60), (20, 127), (28, 60), (29, 256), (31, 1),

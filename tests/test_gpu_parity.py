@@ -29,7 +29,8 @@ def _tol(ref_est, g):
 def _pair(cfg, partition=None):
     p = cfg.partition if partition is None else partition
     gpu = Sketch(cfg, device="cuda")
-    ref = OracleSketch(cfg.log2_pool, cfg.width, cfg.k, cfg.g, cfg.seed_a, cfg.seed_b, p)
+    ref = OracleSketch(cfg.log2_pool, cfg.width, cfg.k, cfg.g, cfg.seed_a, cfg.seed_b, p,
+                       cfg.counter, cfg.block_log2)
     return gpu, ref
 
 
@@ -432,6 +433,51 @@ def test_partitioned_geometries(c, w, k, g, partition, n_hosts):
         gen = torch.Generator().manual_seed(k)
         theta = (torch.randn(_lib.MLP_PARAMS, generator=gen) * 0.05).cuda()
         wts = L.pack(theta, L.new_weights())
+        d_learn, d_cf = L.estimate_learned(gpu, hosts, wts)
+        p_learn, p_cf = L.estimate_learned(gpu, hosts, wts, partitioned=True)
+        torch.cuda.synchronize()
+        assert torch.equal(d_cf, p_cf) and torch.equal(d_learn, p_learn)
+
+
+@pytest.mark.parametrize("c,w,k,g,b,n_hosts", [
+    (20, 8, 60, 1024, 6, 1000),     # 64-VAT blocks: one 64-byte segment of the pool
+    (16, 4, 7, 100, 3, 500),        # g not a multiple of the block
+    (22, 7, 60, 512, 5, 700),       # exact 7-bit ATs
+    (12, 8, 9, 64, 6, 300),         # blocks as large as a host's VAT set
+    (24, 8, 30, 3000, 5, 400),      # 32-VAT blocks, more blocks per host than lanes, ragged last block
+])
+def test_blocked_h_parity(c, w, k, g, b, n_hosts):
+    """Locality-blocked H (opt-in): pool state, live counts, histograms and
+    estimates equal the oracle's on both estimate paths; the learned estimate
+    is identical on both paths."""
+    rng = np.random.default_rng(c * 100 + b)
+    cfg = Config(c, w, k, g, seed_a=c, seed_b=b, block_log2=b)
+    gpu, ref = _pair(cfg)
+    hosts = rng.integers(0, 2**32, size=n_hosts, dtype=np.uint64).astype(np.uint32)
+    for t in range(min(2 * k + 3, 30)):
+        n = int(rng.integers(1, 30_000))
+        pairs = np.stack([hosts[rng.integers(0, hosts.size, size=n)],
+                          rng.integers(0, 2**32, size=n, dtype=np.uint64).astype(np.uint32)], 1)
+        gpu.ingest(pairs)
+        ref.ingest(pairs)
+        gpu.close_slice()
+        ref.close_slice()
+        if t % 5 == 4:
+            _check_state(gpu, ref, f"blocked slice {t}")
+    _check_state(gpu, ref, "blocked end")
+    for kp in sorted({1, max(1, k // 2), k}):
+        _check_estimates(gpu, ref, hosts, kprime=kp, hist=(kp == k), what=f"blocked k'={kp}")
+    # window k without histograms: the whole-block popcount gather when blocks are >= 32 VATs
+    r_est, r_live, _ = ref.estimate(hosts)
+    est, live, _ = gpu.estimate(hosts)
+    torch.cuda.synchronize()
+    assert np.array_equal(_u32(live), r_live)
+    e = est.cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(e - r_est) <= _tol(r_est, ref.g))
+    if k + 3 <= _lib.MLP_FEATURES:
+        from paper_1812_00282_amd import learned as L
+        gen = torch.Generator().manual_seed(b)
+        wts = L.pack((torch.randn(_lib.MLP_PARAMS, generator=gen) * 0.05).cuda(), L.new_weights())
         d_learn, d_cf = L.estimate_learned(gpu, hosts, wts)
         p_learn, p_cf = L.estimate_learned(gpu, hosts, wts, partitioned=True)
         torch.cuda.synchronize()

@@ -168,12 +168,13 @@ def test_check_at_k9_distances():
 # ------------------------------------------- AT state vs 64-bit timestamps --
 
 def _ts_run(c, k, partition, seed, n_slices, per_slice, n_hosts=40, g=16,
-            empty_every=0):
+            empty_every=0, block_log2=0):
     """Drive the oracle and a TS pool with the same random stream and compare
     at every slice end: CheckAT of every slot for every k' (Thm. 1, Cor. 1),
     the census, and each host's live count and distance histogram."""
     rng = np.random.default_rng(seed)
-    s = OracleSketch(c, 16, k, g, seed_a=seed, seed_b=seed + 1, partition=partition)
+    s = OracleSketch(c, 16, k, g, seed_a=seed, seed_b=seed + 1, partition=partition,
+                     block_log2=block_log2)
     N = s.N
     ts = brute.TSPool(N)
     hosts = rng.integers(0, 2**32, size=n_hosts, dtype=np.uint64).astype(np.uint32)
@@ -231,6 +232,31 @@ def test_at_state_matches_timestamps_long_sparse():
     _ts_run(8, 5, 0, seed=77, n_slices=60, per_slice=20, n_hosts=10, g=8)
 
 
+@pytest.mark.parametrize("k,b", [(4, 2), (9, 3)])
+def test_at_state_matches_timestamps_blocked_h(k, b):
+    """The AT state machine does not depend on where H puts the VATs: with
+    the locality-blocked H the pool still equals the timestamp pool."""
+    _ts_run(8, k, 0, seed=31 * k + b, n_slices=3 * k + 4, per_slice=150, block_log2=b)
+
+
+def test_blocked_h_structure():
+    """Locality-blocked H with blocks of 2^b VATs: VAT i lands in slot i mod 2^b
+    of a block whose index is the independent H of a pool of 2^(c-b) ATs
+    evaluated at VAT index floor(i / 2^b); b = 0 is the independent H."""
+    rng = np.random.default_rng(8)
+    for b in range(0, 7):
+        for _ in range(300):
+            c = int(rng.integers(max(b, 1), 33))
+            seed, aip = int(rng.integers(0, 2**32)), int(rng.integers(0, 2**32))
+            i = int(rng.integers(0, 1 << 14))
+            got = vate_ref.hash_H_blocked(c, b, seed, aip, i)
+            if b == 0:
+                assert got == vate_ref.hash_H(c, seed, aip, i)
+            else:
+                base = vate_ref.hash_H(c - b, seed, aip, i >> b)
+                assert got == (base << b) | (i & ((1 << b) - 1))
+
+
 # -------------------------------------------------------------- estimate --
 
 def test_estimate_reduces_to_linear_counting():
@@ -278,6 +304,36 @@ def test_estimate_accuracy_on_loaded_pool():
         assert abs(rel.mean() - 1.0) < 4 * se / math.sqrt(sel.sum()) + 0.01, (n, rel.mean())
         # without the pool term the mean would be off by g ln(1/Z_p) / n
         assert g * math.log(1 / zp) / n > 8 * se / math.sqrt(sel.sum())
+
+
+def test_blocked_h_accuracy_cost():
+    """The locality-blocked H keeps the estimate unbiased but spreads it: the
+    VATs of a block share their neighbours' traffic, so the noise of Z_v is
+    no longer averaged over g independent slots.  Same loaded pool as above;
+    the mean stays within 6 observed standard errors of the truth for 64-VAT
+    blocks, and the spread at n = 200 exceeds the independent H's."""
+    c, k, g = 18, 4, 1024
+    rng0 = np.random.default_rng(123)
+    bg_hosts = rng0.integers(0, 2**32, size=3000, dtype=np.uint64).astype(np.uint32)
+    bg = np.stack([bg_hosts[rng0.integers(0, 3000, size=70000)],
+                   rng0.integers(0, 2**32, size=70000, dtype=np.uint64).astype(np.uint32)], 1)
+    probes = rng0.integers(0, 2**32, size=300, dtype=np.uint64).astype(np.uint32)
+    truths = np.array([50, 200, 800] * 100)
+    pp = [np.stack([np.full(n, h, dtype=np.uint32),
+                    rng0.integers(0, 2**32, size=n, dtype=np.uint64).astype(np.uint32)], 1)
+          for h, n in zip(probes, truths)]
+    pairs = np.concatenate([bg] + pp)
+    spread = {}
+    for b in (0, 6):
+        s = OracleSketch(c, 8, k, g, seed_a=5, seed_b=6, block_log2=b)
+        s.ingest(pairs)
+        s.close_slice()
+        est, _, _ = s.estimate(probes)
+        for n in (50, 200, 800):
+            rel = est[truths == n] / n
+            assert abs(rel.mean() - 1.0) < 6 * rel.std() / math.sqrt(rel.size) + 0.02, (b, n)
+            spread[b, n] = rel.std()
+    assert spread[6, 200] > 1.5 * spread[0, 200]
 
 
 def test_estimate_accuracy_small_workload():
