@@ -143,21 +143,42 @@ int vate_estimate(vate_sketch *s, const uint32_t *hosts_dev, size_t n_hosts,
                   uint32_t *hist_dev, void *stream);
 
 /* Device workspace (bytes) that vate_estimate_ws needs for n_hosts hosts:
- * about 4*g bytes per host (one 32-bit entry per VAT) plus small tables.
- * Errors: VATE_E_INVAL. */
+ * about 6*g bytes per host (a 32-bit entry and a 16-bit result per VAT, runs
+ * padded to 4) plus small tables.  Errors: VATE_E_INVAL. */
 int vate_estimate_workspace_bytes(const vate_sketch *s, size_t n_hosts, size_t *bytes);
 
 /* Same results as vate_estimate (same outputs, layouts, errors; any k for the
- * histogram), computed with the VAT lookups reordered for locality: the
- * hosts' VATs are first written to the workspace grouped by pool slice of
- * 2^20 ATs, then each slice's lookups are resolved against that slice of the
- * activity bitmap held in LDS.  workspace_dev (256-byte aligned, at least
- * vate_estimate_workspace_bytes) is scratch owned by the caller; calls that
- * share a workspace must not overlap.  Errors: as vate_estimate, plus
- * VATE_E_INVAL for a missing or small workspace. */
+ * histogram), computed with the VAT lookups (Alg. 4's estimate loop, Alg. 1)
+ * reordered for locality: the hosts' VATs are hashed once and sorted into
+ * the workspace by pool slice of 128 KiB of ATs, each slice's lookups are
+ * resolved against that slice of the pool held in LDS, and every host's
+ * distance histogram is rebuilt from the results.  workspace_dev (256-byte
+ * aligned, at least vate_estimate_workspace_bytes) is scratch owned by the
+ * caller; calls that share a workspace must not overlap.  Sketches outside
+ * the path's limits (pools above 1 GiB, g above the sort's capacity, the
+ * locality-blocked H) fall back to vate_estimate's gather.  Errors: as
+ * vate_estimate, plus VATE_E_INVAL for a missing or small workspace. */
 int vate_estimate_ws(vate_sketch *s, const uint32_t *hosts_dev, size_t n_hosts,
                      uint32_t kprime, float *est_dev, uint32_t *live_dev, uint32_t *hist_dev,
                      void *workspace_dev, size_t workspace_bytes, void *stream);
+
+/* vate_estimate_ws in two parts, for a host list that stays the same from
+ * slice to slice (the monitored hosts of Alg. 4's ANet): the VAT addresses
+ * depend only on the hosts and H, not on the pool, so
+ *   vate_estimate_plan hashes and sorts the hosts' VATs into the workspace
+ *     (any slice phase; hosts_dev is read during the call's stream work only),
+ *   vate_estimate_run answers a closed slice from that plan (lookups and
+ *     histograms only) with vate_estimate_ws's outputs and layouts.
+ * The plan belongs to the sketch and to this workspace and host count; it
+ * stays valid until the workspace is used by another estimate call.  A
+ * changed host list needs a new plan.  Errors: VATE_E_UNSUPPORTED (plan for a
+ * sketch outside the partitioned path), VATE_E_STATE (run without a plan for
+ * this workspace and n_hosts, or slice not closed), VATE_E_INVAL, VATE_E_DEVICE. */
+int vate_estimate_plan(vate_sketch *s, const uint32_t *hosts_dev, size_t n_hosts,
+                       void *workspace_dev, size_t workspace_bytes, void *stream);
+int vate_estimate_run(vate_sketch *s, size_t n_hosts, uint32_t kprime, float *est_dev,
+                      uint32_t *live_dev, uint32_t *hist_dev, void *workspace_dev,
+                      size_t workspace_bytes, void *stream);
 
 /* Estimates for several windows k'_1 < ... < k'_m (m <= 64, each in [1, k],
  * given in host memory) from one pass over each host's VATs: any window up

@@ -95,6 +95,13 @@ int vate_estimate_learned_ws(vate_sketch *s, const uint32_t *hosts_dev, size_t n
                              const void *weights_dev, float *est_dev, float *est_cf_dev,
                              void *workspace_dev, size_t workspace_bytes, void *stream);
 
+/* vate_estimate_learned_ws from a host plan made by vate_estimate_plan (vate.h)
+ * in a workspace of at least vate_estimate_learned_workspace_bytes: the
+ * lookups, histograms and network only.  Errors: as vate_estimate_run. */
+int vate_estimate_learned_run(vate_sketch *s, size_t n_hosts, const void *weights_dev,
+                              float *est_dev, float *est_cf_dev, void *workspace_dev,
+                              size_t workspace_bytes, void *stream);
+
 /* Diagnostic: D = A * B on the matrix cores for one 16x32 (A) by 32x16 (B)
  * tile, A and B row-major bf16, D row-major FP32 - checks the fragment
  * layout the kernels assume. */

@@ -55,6 +55,8 @@ _SIGS = {
     "vate_read_census": (_i32, [_vp, _vp, _vp]),
     "vate_estimate_workspace_bytes": (_i32, [_vp, _sz, ctypes.POINTER(_sz)]),
     "vate_estimate_ws": (_i32, [_vp, _vp, _sz, _u32, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "vate_estimate_plan": (_i32, [_vp, _vp, _sz, _vp, _sz, _vp]),
+    "vate_estimate_run": (_i32, [_vp, _sz, _u32, _vp, _vp, _vp, _vp, _sz, _vp]),
     "vate_estimate_multi_workspace_bytes": (_i32, [_vp, _sz, ctypes.POINTER(_sz)]),
     "vate_estimate_multi_ws": (_i32, [_vp, _vp, _sz, _vp, _u32, _vp, _vp, _sz, _vp]),
     "vate_read_state": (_i32, [_vp, _vp, ctypes.POINTER(_u64), ctypes.POINTER(_u32),
@@ -76,6 +78,7 @@ _SIGS = {
     "vate_estimate_learned": (_i32, [_vp, _vp, _sz, _vp, _vp, _vp, _vp]),
     "vate_estimate_learned_workspace_bytes": (_i32, [_vp, _sz, ctypes.POINTER(_sz)]),
     "vate_estimate_learned_ws": (_i32, [_vp, _vp, _sz, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "vate_estimate_learned_run": (_i32, [_vp, _sz, _vp, _vp, _vp, _vp, _sz, _vp]),
     "vate_mlp_mfma_selftest": (_i32, [_vp, _vp, _vp, _vp]),
 }
 

@@ -727,6 +727,8 @@ struct vate_sketch {
     int closed;                  // 1: slice ended, estimates allowed
     int dead;                    // sticky device error
     uint32_t lds_budget;         // dynamic LDS a partitioned-scatter workgroup may use (bytes)
+    const void *plan_ws;         // workspace holding a host plan (vate_estimate_plan), or null
+    uint64_t plan_n;             // its host count
     char err[256];
 };
 
@@ -974,10 +976,14 @@ static int set_lds_limit(vate_sketch *s, const void *fn, uint32_t bytes)
     return VATE_OK;
 }
 
+// PART_ALL: scatter, lookup, finalize; PART_PLAN: the scatter only (the
+// host plan); PART_RUN: lookup and finalize from an existing plan.
+enum PartSteps { PART_ALL = 0, PART_PLAN = 1, PART_RUN = 2 };
+
 template <int W, int MODE>
 static int launch_part(vate_sketch *s, const PartGeo &pg, void *ws, const uint32_t *hosts, uint32_t n,
                        uint32_t kprime, float *est, uint32_t *live, uint32_t *hist, const Windows &win,
-                       const void *weights, float *cf, hipStream_t st)
+                       const void *weights, float *cf, hipStream_t st, int steps = PART_ALL)
 {
     static bool attr = false;
     if (!attr) {
@@ -990,7 +996,9 @@ static int launch_part(vate_sketch *s, const PartGeo &pg, void *ws, const uint32
         attr = true;
     }
     const RunWs w = run_ws(pg, s->p.k, ws, MODE == kFinLearned);
-    k_run_scatter<<<pg.n_sub, kRunThreads, pg.lds_scatter, st>>>(s->G, pg, hosts, n, w.entries, w.table);
+    if (steps != PART_RUN)
+        k_run_scatter<<<pg.n_sub, kRunThreads, pg.lds_scatter, st>>>(s->G, pg, hosts, n, w.entries, w.table);
+    if (steps == PART_PLAN) return VATE_OK;
     k_run_lookup<W><<<pg.n_slices, kRunThreads, pg.lds_lookup, st>>>(s->G, pg, s->pool, s->st, w.entries, w.table,
                                                                        w.res);
     if (MODE == kFinMulti) k_census_prefix<<<1, 64, 0, st>>>(s->G, s->st, w.cum);
@@ -1006,11 +1014,12 @@ static int launch_part(vate_sketch *s, const PartGeo &pg, void *ws, const uint32
 template <int MODE>
 static int launch_part_w(vate_sketch *s, const PartGeo &pg, void *ws, const uint32_t *hosts, uint32_t n,
                          uint32_t kprime, float *est, uint32_t *live, uint32_t *hist, const Windows &win,
-                         const void *weights, float *cf, hipStream_t st)
+                         const void *weights, float *cf, hipStream_t st, int steps = PART_ALL)
 {
+    if (steps == PART_ALL && ws == s->plan_ws) s->plan_ws = nullptr;   // the plan is overwritten
     return by_width(s->p.width, [&](auto W) {
         return launch_part<decltype(W)::value, MODE>(s, pg, ws, hosts, n, kprime, est, live, hist, win, weights, cf,
-                                                     st);
+                                                     st, steps);
     });
 }
 
@@ -1175,6 +1184,83 @@ int vate_estimate_ws(vate_sketch *s, const uint32_t *hosts_dev, size_t n_hosts, 
                                                  hist_dev, Windows{}, nullptr, nullptr, st);
     if (rc != VATE_OK) return rc;
     return check_launch(s, "estimate_ws");
+}
+
+int vate_estimate_plan(vate_sketch *s, const uint32_t *hosts_dev, size_t n_hosts, void *workspace_dev,
+                       size_t workspace_bytes, void *stream)
+{
+    if (!s) return VATE_E_INVAL;
+    if (s->dead) return VATE_E_DEVICE;
+    if (n_hosts == 0 || n_hosts > 0xFFFFFFFFull - 1024) return fail(s, VATE_E_INVAL, "need 1 .. 2^32-1025 hosts");
+    PartGeo pg;
+    if (!part_geo(s, n_hosts, &pg))
+        return fail(s, VATE_E_UNSUPPORTED, "no partitioned plan for this sketch (use vate_estimate)");
+    size_t need = 0;
+    vate_estimate_workspace_bytes(s, n_hosts, &need);
+    if (!workspace_dev || workspace_bytes < need || (reinterpret_cast<uintptr_t>(workspace_dev) & 255u))
+        return fail(s, VATE_E_INVAL, "workspace missing, too small or not 256-byte aligned");
+    if (!hosts_dev || (reinterpret_cast<uintptr_t>(hosts_dev) & 3u))
+        return fail(s, VATE_E_INVAL, "hosts must be non-NULL and 4-byte aligned");
+    const int rc = launch_part_w<kFinClosedForm>(s, pg, workspace_dev, hosts_dev, (uint32_t)n_hosts, s->p.k, nullptr,
+                                                 nullptr, nullptr, Windows{}, nullptr, nullptr,
+                                                 static_cast<hipStream_t>(stream), PART_PLAN);
+    if (rc != VATE_OK) return rc;
+    s->plan_ws = workspace_dev;
+    s->plan_n = n_hosts;
+    return check_launch(s, "estimate_plan");
+}
+
+// A run needs a closed slice and the plan made for this workspace and host count.
+static int check_plan(vate_sketch *s, size_t n_hosts, const void *workspace_dev, size_t workspace_bytes, size_t need,
+                      PartGeo *pg)
+{
+    if (s->dead) return VATE_E_DEVICE;
+    if (!s->closed) return fail(s, VATE_E_STATE, "estimate needs a closed slice (call vate_close_slice)");
+    if (!workspace_dev || workspace_dev != s->plan_ws || n_hosts != s->plan_n)
+        return fail(s, VATE_E_STATE, "no plan for this workspace and host count (call vate_estimate_plan)");
+    if (workspace_bytes < need) return fail(s, VATE_E_INVAL, "workspace too small");
+    if (!part_geo(s, n_hosts, pg)) return fail(s, VATE_E_STATE, "plan geometry unavailable");
+    return VATE_OK;
+}
+
+int vate_estimate_run(vate_sketch *s, size_t n_hosts, uint32_t kprime, float *est_dev, uint32_t *live_dev,
+                      uint32_t *hist_dev, void *workspace_dev, size_t workspace_bytes, void *stream)
+{
+    if (!s) return VATE_E_INVAL;
+    if (kprime < 1 || kprime > s->p.k) return fail(s, VATE_E_INVAL, "k' must be in [1, k]");
+    size_t need = 0;
+    vate_estimate_workspace_bytes(s, n_hosts, &need);
+    PartGeo pg;
+    int rc = check_plan(s, n_hosts, workspace_dev, workspace_bytes, need, &pg);
+    if (rc != VATE_OK) return rc;
+    if (!est_dev || (reinterpret_cast<uintptr_t>(est_dev) & 3u) || (reinterpret_cast<uintptr_t>(live_dev) & 3u) ||
+        (reinterpret_cast<uintptr_t>(hist_dev) & 3u))
+        return fail(s, VATE_E_INVAL, "est/live/hist must be 4-byte aligned, est non-NULL");
+    rc = launch_part_w<kFinClosedForm>(s, pg, workspace_dev, nullptr, (uint32_t)n_hosts, kprime, est_dev, live_dev,
+                                       hist_dev, Windows{}, nullptr, nullptr, static_cast<hipStream_t>(stream),
+                                       PART_RUN);
+    if (rc != VATE_OK) return rc;
+    return check_launch(s, "estimate_run");
+}
+
+int vate_estimate_learned_run(vate_sketch *s, size_t n_hosts, const void *weights_dev, float *est_dev,
+                              float *est_cf_dev, void *workspace_dev, size_t workspace_bytes, void *stream)
+{
+    if (!s) return VATE_E_INVAL;
+    if (s->p.k > (uint32_t)kLearnMaxK) return fail(s, VATE_E_UNSUPPORTED, "learned estimator needs k + 3 <= 64");
+    size_t need = 0;
+    vate_estimate_learned_workspace_bytes(s, n_hosts, &need);
+    PartGeo pg;
+    int rc = check_plan(s, n_hosts, workspace_dev, workspace_bytes, need, &pg);
+    if (rc != VATE_OK) return rc;
+    if (!est_dev || !est_cf_dev || !weights_dev || (reinterpret_cast<uintptr_t>(est_dev) & 3u) ||
+        (reinterpret_cast<uintptr_t>(est_cf_dev) & 3u) || (reinterpret_cast<uintptr_t>(weights_dev) & 255u))
+        return fail(s, VATE_E_INVAL, "est/est_cf must be 4-byte and weights 256-byte aligned, non-NULL");
+    rc = launch_part_w<kFinLearned>(s, pg, workspace_dev, nullptr, (uint32_t)n_hosts, s->p.k, est_dev, nullptr,
+                                    nullptr, Windows{}, weights_dev, est_cf_dev, static_cast<hipStream_t>(stream),
+                                    PART_RUN);
+    if (rc != VATE_OK) return rc;
+    return check_launch(s, "estimate_learned_run");
 }
 
 int vate_estimate_learned_ws(vate_sketch *s, const uint32_t *hosts_dev, size_t n_hosts, const void *weights_dev,

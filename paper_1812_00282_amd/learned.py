@@ -115,6 +115,21 @@ def estimate_learned(sk: Sketch, hosts, weights, stream=None, out=None, partitio
     return est, cf
 
 
+def estimate_learned_run(sk: Sketch, weights, stream=None, out=None):
+    """estimate_learned for the hosts planned with sk.plan(...)
+    (vate_estimate_learned_run)."""
+    n = sk._plan_n
+    if out is None:
+        est = torch.empty(n, dtype=torch.float32, device=sk.device)
+        cf = torch.empty(n, dtype=torch.float32, device=sk.device)
+    else:
+        est, cf = out
+    check(lib().vate_estimate_learned_run(sk.handle, n, weights.data_ptr(), est.data_ptr(), cf.data_ptr(),
+                                          sk._pws.data_ptr(), sk._pws.numel(), _stream_handle(stream)),
+          sk.handle)
+    return est, cf
+
+
 def mfma_selftest(a_bf16: torch.Tensor, b_bf16: torch.Tensor) -> torch.Tensor:
     d = torch.empty((16, 16), dtype=torch.float32, device=a_bf16.device)
     check(lib().vate_mlp_mfma_selftest(a_bf16.data_ptr(), b_bf16.data_ptr(), d.data_ptr(),

@@ -133,6 +133,40 @@ class Sketch:
         self._keep_h = ht
         return est, live, hist
 
+    def plan(self, hosts, stream=None) -> None:
+        """Hash and sort the VATs of a host list that stays the same across
+        slices (vate_estimate_plan); estimate_run / learned.estimate_learned_run
+        then answer each closed slice from the plan.  The plan lives in a
+        workspace owned by the sketch, sized for the learned estimate too."""
+        ht = as_u32_tensor(hosts, self.device)
+        n = ht.numel()
+        b = ctypes.c_size_t()
+        check(lib().vate_estimate_learned_workspace_bytes(self._h, n, ctypes.byref(b)), self._h)
+        if getattr(self, "_pws", None) is None or self._pws.numel() < b.value:
+            self._pws = torch.empty(b.value, dtype=torch.uint8, device=self.device)
+        check(lib().vate_estimate_plan(self._h, ht.data_ptr(), n, self._pws.data_ptr(), self._pws.numel(),
+                                       _stream_handle(stream)), self._h)
+        self._plan_n = n
+        self._keep_plan_hosts = ht
+
+    def estimate_run(self, kprime: int | None = None, want_live: bool = True, want_hist: bool = False,
+                     stream=None, out=None):
+        """vate_estimate_run: the outputs of estimate(...) for the planned hosts."""
+        n = self._plan_n
+        kp = self.cfg.k if kprime is None else kprime
+        if out is not None:
+            est, live, hist = out
+        else:
+            est = torch.empty(n, dtype=torch.float32, device=self.device)
+            live = torch.empty(n, dtype=torch.int32, device=self.device) if want_live else None
+            hist = (torch.empty((n, self.cfg.k + 1), dtype=torch.int32, device=self.device)
+                    if want_hist else None)
+        check(lib().vate_estimate_run(self._h, n, kp, est.data_ptr(),
+                                      live.data_ptr() if live is not None else None,
+                                      hist.data_ptr() if hist is not None else None,
+                                      self._pws.data_ptr(), self._pws.numel(), _stream_handle(stream)), self._h)
+        return est, live, hist
+
     def estimate_windows(self, hosts, kprimes, stream=None) -> torch.Tensor:
         """Estimates for several windows (ascending k' values) from one pass:
         float32 tensor [hosts][windows]."""

@@ -484,6 +484,61 @@ def test_blocked_h_parity(c, w, k, g, b, n_hosts):
         assert torch.equal(d_cf, p_cf) and torch.equal(d_learn, p_learn)
 
 
+def test_planned_estimates_equal_unplanned():
+    """A host plan made once (before the first slice) answers every later
+    slice exactly as the unplanned partitioned estimate does, closed form,
+    histograms and learned; runs without a plan, for another host count or
+    after the workspace was reused are refused."""
+    from paper_1812_00282_amd import learned as L
+    cfg = Config(22, 8, 20, 512, seed_a=3, seed_b=4)
+    gpu, ref = _pair(cfg)
+    rng = np.random.default_rng(21)
+    hosts = rng.integers(0, 2**32, size=2000, dtype=np.uint64).astype(np.uint32)
+    gpu.plan(hosts)
+    gen = torch.Generator().manual_seed(5)
+    wts = L.pack((torch.randn(_lib.MLP_PARAMS, generator=gen) * 0.05).cuda(), L.new_weights())
+    for t in range(26):
+        n = int(rng.integers(1, 40_000))
+        pairs = np.stack([hosts[rng.integers(0, hosts.size, size=n)],
+                          rng.integers(0, 2**32, size=n, dtype=np.uint64).astype(np.uint32)], 1)
+        gpu.ingest(pairs)
+        ref.ingest(pairs)
+        gpu.close_slice()
+        ref.close_slice()
+        if t % 5 != 4:
+            continue
+        for kp in (cfg.k // 2, cfg.k):
+            e1, l1, h1 = gpu.estimate_run(kprime=kp, want_hist=(kp == cfg.k))
+            e2, l2, h2 = gpu.estimate(hosts, kprime=kp, want_hist=(kp == cfg.k), partitioned=True)
+            torch.cuda.synchronize()
+            assert torch.equal(e1, e2) and torch.equal(l1, l2), (t, kp)
+            if h1 is not None:
+                assert torch.equal(h1, h2)
+            r_est, r_live, _ = ref.estimate(hosts, kprime=kp)
+            assert np.array_equal(_u32(l1), r_live)
+        p_learn, p_cf = L.estimate_learned_run(gpu, wts)
+        q_learn, q_cf = L.estimate_learned(gpu, hosts, wts, partitioned=True)
+        torch.cuda.synchronize()
+        assert torch.equal(p_learn, q_learn) and torch.equal(p_cf, q_cf)
+    lib = _lib.lib()
+    est = torch.empty(hosts.size, dtype=torch.float32, device="cuda")
+    ws = gpu._pws
+    assert lib.vate_estimate_run(gpu.handle, hosts.size + 1, cfg.k, est.data_ptr(), None, None,
+                                 ws.data_ptr(), ws.numel(), None) == _lib.VATE_E_STATE
+    other = Sketch(cfg)
+    other.ingest(np.zeros((0, 2), dtype=np.uint32))
+    other.close_slice()
+    assert lib.vate_estimate_run(other.handle, hosts.size, cfg.k, est.data_ptr(), None, None,
+                                 ws.data_ptr(), ws.numel(), None) == _lib.VATE_E_STATE
+    # an unplanned estimate into the plan's workspace ends the plan
+    h = torch.from_numpy(hosts.view(np.int32)).cuda()
+    assert lib.vate_estimate_ws(gpu.handle, h.data_ptr(), hosts.size, cfg.k, est.data_ptr(), None, None,
+                                ws.data_ptr(), ws.numel(), None) == _lib.VATE_OK
+    assert lib.vate_estimate_run(gpu.handle, hosts.size, cfg.k, est.data_ptr(), None, None,
+                                 ws.data_ptr(), ws.numel(), None) == _lib.VATE_E_STATE
+    torch.cuda.synchronize()
+
+
 @pytest.mark.parametrize("w,k,c", [(4, 7, 12), (8, 60, 16), (16, 300, 16), (9, 300, 16), (6, 60, 14)])
 def test_vdre_matches_oracle_and_vate(w, k, c):
     """Distance-recorder counters (the paper's VDRE baseline, full-pool
