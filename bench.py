@@ -351,6 +351,8 @@ def main() -> int:
                 "kernel": "estimate phase: k_run_scatter + k_run_lookup<8> + k_run_finalize + k_learned_rows",
                 "algorithmic_bytes_per_launch": bytes_per_host * pop.n_hosts,
                 "avg_launch_ms": est_ms,
+                "traffic_gbs": traffic / (est_ms * 1e-3) / 1e9 if traffic else None,
+                "traffic_frac": traffic / (est_ms * 1e-3) / 1e9 / HBM_PEAK_GBS if traffic else None,
                 "random_lines_per_s": wl.g * pop.n_hosts / (est_ms * 1e-3)}
 
     line = {
