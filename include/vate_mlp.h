@@ -84,7 +84,7 @@ int vate_estimate_learned(vate_sketch *s, const uint32_t *hosts_dev, size_t n_ho
                           void *stream);
 
 /* Workspace (bytes) for vate_estimate_learned_ws with n_hosts hosts: that of
- * vate_estimate_ws plus one (k+1)-bin histogram per host. */
+ * vate_estimate_ws plus one packed 16-bit (k+1)-bin histogram row per host. */
 int vate_estimate_learned_workspace_bytes(const vate_sketch *s, size_t n_hosts, size_t *bytes);
 
 /* Same outputs as vate_estimate_learned, with the VAT lookups of

@@ -934,6 +934,12 @@ static bool part_geo(const vate_sketch *s, uint64_t n, PartGeo *out)
     p.lds_scatter = (uint32_t)lds_for(hosts);
     p.lds_lookup = (uint32_t)(((((uint64_t)w << sl) >> 3) + 15) & ~15ull);
     p.lds_final = p.hosts * p.rowp * 4u;
+    // Each slice's walk over the subgroups is cut into kLookupSplit ranges
+    // (whole 1024-subgroup steps), one workgroup each: the eight workgroups of
+    // a super-slice then work on the same subgroups at about the same time,
+    // so the result lines they share meet in L2 more often.
+    p.split = std::max<uint32_t>(1u, std::min<uint32_t>(kLookupSplit, (p.n_sub + 1023u) / 1024u));
+    p.span = ((p.n_sub + p.split - 1u) / p.split + 1023u) & ~1023u;
     *out = p;
     return true;
 }
@@ -999,8 +1005,8 @@ static int launch_part(vate_sketch *s, const PartGeo &pg, void *ws, const uint32
     if (steps != PART_RUN)
         k_run_scatter<<<pg.n_sub, kRunThreads, pg.lds_scatter, st>>>(s->G, pg, hosts, n, w.entries, w.table);
     if (steps == PART_PLAN) return VATE_OK;
-    k_run_lookup<W><<<pg.n_slices, kRunThreads, pg.lds_lookup, st>>>(s->G, pg, s->pool, s->st, w.entries, w.table,
-                                                                       w.res);
+    k_run_lookup<W><<<pg.n_slices * pg.split, kRunThreads, pg.lds_lookup, st>>>(s->G, pg, s->pool, s->st, w.entries,
+                                                                                  w.table, w.res);
     if (MODE == kFinMulti) k_census_prefix<<<1, 64, 0, st>>>(s->G, s->st, w.cum);
     k_run_finalize<MODE><<<pg.n_sub, kFinThreads, pg.lds_final, st>>>(
         s->G, pg, s->st, n, kprime, w.res, w.table, est, live, MODE == kFinLearned ? w.rows : hist, win, w.cum,

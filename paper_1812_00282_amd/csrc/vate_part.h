@@ -41,6 +41,7 @@ constexpr uint32_t kRunMaxHosts = 1024;                         // hosts per sub
 constexpr uint32_t kRunPad = 0xFFFFFFFFu;                       // padding entry (never a real one: <= 28 bits)
 constexpr uint32_t kSuper = 8;                                  // slices per super-slice
 constexpr uint32_t kFinThreads = 256;
+constexpr uint32_t kLookupSplit = 2;                            // subgroup ranges per slice (lookup)
 constexpr uint32_t kFinHistBytes = 64u * 1024u;                 // per-subgroup histogram ceiling
 
 struct PartGeo {
@@ -57,6 +58,8 @@ struct PartGeo {
     uint32_t fast;        // every block holds >= 2^sl ATs: a slice meets at most two blocks
     uint32_t rowp;        // u32 words per packed 16-bit histogram row, ceil((k + 1) / 2)
     uint32_t xcd;         // map the slices of a super-slice to one XCD
+    uint32_t split;       // lookup workgroups per slice, each over a range of subgroups
+    uint32_t span;        // subgroups per range (a multiple of 1024)
     uint32_t lds_scatter, lds_lookup, lds_final;
     uint32_t dbits;       // distance bits of a result: values 0..k, all ones = padding
 };
@@ -221,14 +224,20 @@ __global__ void __launch_bounds__(kRunThreads) k_run_lookup(Geo G, PartGeo PG, c
     extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
     const uint8_t *at = reinterpret_cast<const uint8_t *>(lds);
     uint32_t B, j;
+    uint32_t part;                                  // subgroup range of this workgroup
     if (PG.xcd) {              // workgroup x runs on XCD x mod 8
         const uint32_t r = blockIdx.x & 7u, rest = blockIdx.x >> 3;
         j = rest % PG.sub;
-        B = (rest / PG.sub) * 8u + r;
+        const uint32_t rest2 = rest / PG.sub;
+        part = rest2 % PG.split;
+        B = (rest2 / PG.split) * 8u + r;
     } else {
-        B = blockIdx.x / PG.sub;
         j = blockIdx.x % PG.sub;
+        const uint32_t rest2 = blockIdx.x / PG.sub;
+        part = rest2 % PG.split;
+        B = rest2 / PG.split;
     }
+    const uint32_t s_lo = part * PG.span, s_hi = min(PG.n_sub, s_lo + PG.span);
     const uint32_t b = B * PG.sub + j;
     const uint32_t sl = PG.sl, mask = (1u << sl) - 1u;
     const uint32_t nbytes = (uint32_t)(((uint64_t)(W ? W : G.wb) << sl) >> 3);
@@ -290,7 +299,7 @@ __global__ void __launch_bounds__(kRunThreads) k_run_lookup(Geo G, PartGeo PG, c
     // are already in flight.
     auto bounds = [&](uint32_t s0, uint32_t &st_l, uint32_t &en_l) {
         st_l = en_l = 0;
-        if (s0 + lane < PG.n_sub) {
+        if (s0 + lane < s_hi) {
             const size_t cell = (row + s0 + lane) * PG.sub;
             st_l = table[cell + j];
             en_l = j + 1 < PG.sub ? table[cell + j + 1] : table[(next_row + s0 + lane) * PG.sub];
@@ -325,13 +334,13 @@ __global__ void __launch_bounds__(kRunThreads) k_run_lookup(Geo G, PartGeo PG, c
         }
     };
     const uint32_t step = kRunThreads;            // 16 wavefronts x 64 subgroups
-    uint32_t s0 = wv * 64u;
+    uint32_t s0 = s_lo + wv * 64u;
     uint32_t stA, enA, stB, enB;
     uint4 eA[8];
     bounds(s0, stA, enA);
     issue(s0, stA, enA, eA);
     bounds(s0 + step, stB, enB);
-    for (; s0 < PG.n_sub; s0 += step) {
+    for (; s0 < s_hi; s0 += step) {
         uint4 eB[8];
         issue(s0 + step, stB, enB, eB);
         uint32_t stC, enC;
