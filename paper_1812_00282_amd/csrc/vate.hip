@@ -727,6 +727,7 @@ struct vate_sketch {
     int closed;                  // 1: slice ended, estimates allowed
     int dead;                    // sticky device error
     uint32_t lds_budget;         // dynamic LDS a partitioned-scatter workgroup may use (bytes)
+    uint32_t n_cu;               // compute units of the device
     const void *plan_ws;         // workspace holding a host plan (vate_estimate_plan), or null
     uint64_t plan_n;             // its host count
     char err[256];
@@ -1003,7 +1004,8 @@ static int launch_part(vate_sketch *s, const PartGeo &pg, void *ws, const uint32
     }
     const RunWs w = run_ws(pg, s->p.k, ws, MODE == kFinLearned);
     if (steps != PART_RUN)
-        k_run_scatter<<<pg.n_sub, kRunThreads, pg.lds_scatter, st>>>(s->G, pg, hosts, n, w.entries, w.table);
+        k_run_scatter<<<std::min(pg.n_sub, s->n_cu), kRunThreads, pg.lds_scatter, st>>>(s->G, pg, hosts, n, w.entries,
+                                                                                       w.table);
     if (steps == PART_PLAN) return VATE_OK;
     k_run_lookup<W><<<pg.n_slices * pg.split, kRunThreads, pg.lds_lookup, st>>>(s->G, pg, s->pool, s->st, w.entries,
                                                                                   w.table, w.res);
@@ -1079,6 +1081,10 @@ int vate_create(const vate_params *p, void *pool_dev, void *state_dev, void *str
                 if (hipDeviceGetAttribute(&v, a, dev) == hipSuccess && v > lds) lds = v;
             }
         s->lds_budget = std::min<uint32_t>((uint32_t)lds, kRunLdsMax) - kRunLdsStatic;
+        int cus = 0;
+        s->n_cu = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0
+                      ? (uint32_t)cus
+                      : 256u;
     }
     s->closed = 0;
     s->dead = 0;

@@ -79,129 +79,151 @@ __global__ void __launch_bounds__(kRunThreads) k_run_scatter(Geo G, PartGeo PG, 
     uint32_t *cnt = lds;                  // slice counts, then cursors (16-bit pairs)
     uint32_t *keys = lds + nsp;           // host keys
     uint32_t *sorted = keys + nkp;        // entries sorted by slice, runs padded to 4
-    const uint32_t s = blockIdx.x, t = threadIdx.x;
-    const uint32_t h0 = s * PG.hosts;
-    const uint32_t nh = min(PG.hosts, n - h0);
-    const uint32_t nv = nh * G.g;
-    for (uint32_t q = t; q < nsp; q += kRunThreads) cnt[q] = 0;
-    for (uint32_t h = t; h < nh; h += kRunThreads) keys[h] = host_key(G, hosts[h0 + h]);
-    __syncthreads();
-
-    // VAT v = t + j * kRunThreads is VAT i = v mod g of host v / g.  H's
-    // multiplier i * phi is carried along (mod 2^32); when g divides the
-    // workgroup size, i (and i * phi) stay fixed and only the host advances.
-    // Iterations j < jfull are full for every thread (a uniform branch); the
-    // ragged tail is iteration jfull.  H(aip, i) = top c bits of the mix
-    // (shift = 32 - c is at most 31).
+    const uint32_t t = threadIdx.x;
     const uint32_t mask = (1u << PG.sl) - 1u;
-    const uint32_t host_t = t / G.g, i_t = t - host_t * G.g;
-    const uint32_t jfull = nv / kRunThreads, tail = nv - jfull * kRunThreads;
+    const uint32_t host_t0 = t / G.g, i_t0 = t - host_t0 * G.g;
     const uint32_t d_ik = PG.dr * kPhi, g_ik = G.g * kPhi;
-    uint32_t pid[kRunPerThread];
-    if (PG.dr == 0 && G.blog == 0) {
-        const uint32_t ik = i_t * kPhi;
-#pragma unroll
-        for (uint32_t j = 0; j < kRunPerThread; ++j) {
-            const uint32_t host = host_t + j * PG.dq;
-            if (j < jfull || (j == jfull && t < tail)) {
-                pid[j] = mix(keys[host] ^ ik) >> G.shift;
-                const uint32_t b = pid[j] >> PG.sl;
-                atomicAdd(&cnt[b >> 1], 1u << ((b & 1u) << 4));
-            }
-        }
-    } else if (PG.dr == 0) {                 // locality-blocked H, i fixed
-        const uint32_t bm = (1u << G.blog) - 1u, ikb = (i_t >> G.blog) * kPhi, low = i_t & bm;
-#pragma unroll
-        for (uint32_t j = 0; j < kRunPerThread; ++j) {
-            const uint32_t host = host_t + j * PG.dq;
-            if (j < jfull || (j == jfull && t < tail)) {
-                pid[j] = ((mix(keys[host] ^ ikb) >> G.shift) & ~bm) | low;
-                const uint32_t b = pid[j] >> PG.sl;
-                atomicAdd(&cnt[b >> 1], 1u << ((b & 1u) << 4));
-            }
-        }
-    } else {
-        uint32_t host = host_t, i = i_t, ik = i_t * kPhi;
-#pragma unroll
-        for (uint32_t j = 0; j < kRunPerThread; ++j) {
-            if (j < jfull || (j == jfull && t < tail)) {
-                pid[j] = G.blog ? vat_pid(G, keys[host], i) : mix(keys[host] ^ ik) >> G.shift;
-                const uint32_t b = pid[j] >> PG.sl;
-                atomicAdd(&cnt[b >> 1], 1u << ((b & 1u) << 4));
-            }
-            const bool wrap = i + PG.dr >= G.g;
-            i = i + PG.dr - (wrap ? G.g : 0u);
-            ik = ik + d_ik - (wrap ? g_ik : 0u);
-            host += PG.dq + (wrap ? 1u : 0u);
-        }
-    }
-    __syncthreads();
 
-    // Exclusive scan of the padded slice counts; thread t owns whole counter
-    // words [t pw, (t+1) pw), i.e. slices [2 t pw, 2 (t+1) pw).
-    const uint32_t pw = (nwords + kRunThreads - 1) / kRunThreads;
-    const uint32_t w0 = t * pw;
-    uint32_t mine = 0;
-    for (uint32_t q = 0; q < pw; ++q)
-        if (w0 + q < nwords) {
-            const uint32_t v = cnt[w0 + q];
-            mine += pad4(v & 0xFFFFu) + pad4(v >> 16);
-        }
-    const uint32_t lane = t & 63u, wv = t >> 6;
-    uint32_t incl = mine;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const uint32_t y = __shfl_up(incl, off, 64);
-        if (lane >= (uint32_t)off) incl += y;
+    // Workgroups persist: workgroup x sorts subgroups x, x + grid, ...  The
+    // host ids of its next subgroup are loaded (one per thread: hosts per
+    // subgroup <= workgroup size) while the current one is sorted.
+    uint32_t s = blockIdx.x;
+    for (uint32_t q = t; q < nsp; q += kRunThreads) cnt[q] = 0;
+    if (s < PG.n_sub) {
+        const uint32_t h0 = s * PG.hosts, nh = min(PG.hosts, n - h0);
+        if (t < nh) keys[t] = host_key(G, hosts[h0 + t]);
     }
-    if (lane == 63) wsum[wv] = incl;
     __syncthreads();
-    uint32_t run = incl - mine;
-    for (uint32_t q = 0; q < wv; ++q) run += wsum[q];
-    for (uint32_t q = 0; q < pw; ++q) {
-        const uint32_t w = w0 + q;
-        if (w >= nwords) break;
-        const uint32_t v = cnt[w], c0 = v & 0xFFFFu, c1 = v >> 16;
-        const uint32_t p0 = run, p1 = run + pad4(c0);
-        run = p1 + pad4(c1);
-        cnt[w] = p0 | (p1 << 16);
-        for (uint32_t x = p0 + c0; x < p1; ++x) sorted[x] = kRunPad;
-        for (uint32_t x = p1 + c1; x < run; ++x) sorted[x] = kRunPad;
-    }
-    uint32_t total = 0;
-    for (uint32_t q = 0; q < kRunThreads / 64; ++q) total += wsum[q];
-    __syncthreads();
-    // Run starts to the table, one (super-slice, subgroup) cell per store:
-    // the cursor words are the starts as little-endian u16, slice by slice.
-    if (PG.sub == kSuper) {
-        for (uint32_t B = t; B < PG.n_super; B += kRunThreads)
-            reinterpret_cast<uint4 *>(table)[(size_t)B * PG.n_sub + s] = reinterpret_cast<const uint4 *>(cnt)[B];
-    } else {
-        const uint16_t *starts = reinterpret_cast<const uint16_t *>(cnt);
-        for (uint32_t b = t; b < PG.n_slices; b += kRunThreads)
-            table[((size_t)(b / PG.sub) * PG.n_sub + s) * PG.sub + b % PG.sub] = starts[b];
-    }
-    if (t == 0) table[((size_t)PG.n_super * PG.n_sub + s) * PG.sub] = (uint16_t)total;
-    __syncthreads();
+    for (; s < PG.n_sub; s += gridDim.x) {
+        const uint32_t h0 = s * PG.hosts;
+        const uint32_t nh = min(PG.hosts, n - h0);
+        const uint32_t nv = nh * G.g;
+        const uint32_t sn = s + gridDim.x;
+        const uint32_t nh_next = sn < PG.n_sub ? min(PG.hosts, n - sn * PG.hosts) : 0u;
+        uint32_t aip_next = 0;
+        if (t < nh_next) aip_next = hosts[(size_t)sn * PG.hosts + t];
+        // Opaque per iteration, so the compiler does not hoist the 32 VATs'
+        // LDS addresses out of the loop (they would not fit in registers).
+        uint32_t host_t = host_t0, i_t = i_t0;
+        asm volatile("" : "+v"(host_t), "+v"(i_t));
 
-    {
-        auto place = [&](uint32_t p, uint32_t host) {
-            const uint32_t b = p >> PG.sl, sh16 = (b & 1u) << 4;
-            const uint32_t slot = (atomicAdd(&cnt[b >> 1], 1u << sh16) >> sh16) & 0xFFFFu;
-            sorted[slot] = (host << PG.sl) | (p & mask);
-        };
-        uint32_t host = host_t, i = i_t;
+        // VAT v = t + j * kRunThreads is VAT i = v mod g of host v / g.  H's
+        // multiplier i * phi is carried along (mod 2^32); when g divides the
+        // workgroup size, i (and i * phi) stay fixed and only the host advances.
+        // Iterations j < jfull are full for every thread (a uniform branch); the
+        // ragged tail is iteration jfull.  H(aip, i) = top c bits of the mix
+        // (shift = 32 - c is at most 31).
+        const uint32_t jfull = nv / kRunThreads, tail = nv - jfull * kRunThreads;
+        uint32_t pid[kRunPerThread];
+        if (PG.dr == 0 && G.blog == 0) {
+            const uint32_t ik = i_t * kPhi;
 #pragma unroll
-        for (uint32_t j = 0; j < kRunPerThread; ++j) {
-            if (j < jfull || (j == jfull && t < tail)) place(pid[j], host);
-            const bool wrap = i + PG.dr >= G.g;
-            i = i + PG.dr - (wrap ? G.g : 0u);
-            host += PG.dq + (wrap ? 1u : 0u);
+            for (uint32_t j = 0; j < kRunPerThread; ++j) {
+                const uint32_t host = host_t + j * PG.dq;
+                if (j < jfull || (j == jfull && t < tail)) {
+                    pid[j] = mix(keys[host] ^ ik) >> G.shift;
+                    const uint32_t b = pid[j] >> PG.sl;
+                    atomicAdd(&cnt[b >> 1], 1u << ((b & 1u) << 4));
+                }
+            }
+        } else if (PG.dr == 0) {                 // locality-blocked H, i fixed
+            const uint32_t bm = (1u << G.blog) - 1u, ikb = (i_t >> G.blog) * kPhi, low = i_t & bm;
+#pragma unroll
+            for (uint32_t j = 0; j < kRunPerThread; ++j) {
+                const uint32_t host = host_t + j * PG.dq;
+                if (j < jfull || (j == jfull && t < tail)) {
+                    pid[j] = ((mix(keys[host] ^ ikb) >> G.shift) & ~bm) | low;
+                    const uint32_t b = pid[j] >> PG.sl;
+                    atomicAdd(&cnt[b >> 1], 1u << ((b & 1u) << 4));
+                }
+            }
+        } else {
+            uint32_t host = host_t, i = i_t, ik = i_t * kPhi;
+#pragma unroll
+            for (uint32_t j = 0; j < kRunPerThread; ++j) {
+                if (j < jfull || (j == jfull && t < tail)) {
+                    pid[j] = G.blog ? vat_pid(G, keys[host], i) : mix(keys[host] ^ ik) >> G.shift;
+                    const uint32_t b = pid[j] >> PG.sl;
+                    atomicAdd(&cnt[b >> 1], 1u << ((b & 1u) << 4));
+                }
+                const bool wrap = i + PG.dr >= G.g;
+                i = i + PG.dr - (wrap ? G.g : 0u);
+                ik = ik + d_ik - (wrap ? g_ik : 0u);
+                host += PG.dq + (wrap ? 1u : 0u);
+            }
         }
+        __syncthreads();
+
+        // Exclusive scan of the padded slice counts; thread t owns whole counter
+        // words [t pw, (t+1) pw), i.e. slices [2 t pw, 2 (t+1) pw).
+        const uint32_t pw = (nwords + kRunThreads - 1) / kRunThreads;
+        const uint32_t w0 = t * pw;
+        uint32_t mine = 0;
+        for (uint32_t q = 0; q < pw; ++q)
+            if (w0 + q < nwords) {
+                const uint32_t v = cnt[w0 + q];
+                mine += pad4(v & 0xFFFFu) + pad4(v >> 16);
+            }
+        const uint32_t lane = t & 63u, wv = t >> 6;
+        uint32_t incl = mine;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(incl, off, 64);
+            if (lane >= (uint32_t)off) incl += y;
+        }
+        if (lane == 63) wsum[wv] = incl;
+        __syncthreads();
+        uint32_t run = incl - mine;
+        for (uint32_t q = 0; q < wv; ++q) run += wsum[q];
+        for (uint32_t q = 0; q < pw; ++q) {
+            const uint32_t w = w0 + q;
+            if (w >= nwords) break;
+            const uint32_t v = cnt[w], c0 = v & 0xFFFFu, c1 = v >> 16;
+            const uint32_t p0 = run, p1 = run + pad4(c0);
+            run = p1 + pad4(c1);
+            cnt[w] = p0 | (p1 << 16);
+            for (uint32_t x = p0 + c0; x < p1; ++x) sorted[x] = kRunPad;
+            for (uint32_t x = p1 + c1; x < run; ++x) sorted[x] = kRunPad;
+        }
+        uint32_t total = 0;
+        for (uint32_t q = 0; q < kRunThreads / 64; ++q) total += wsum[q];
+        __syncthreads();
+        // Run starts to the table, one (super-slice, subgroup) cell per store:
+        // the cursor words are the starts as little-endian u16, slice by slice.
+        if (PG.sub == kSuper) {
+            for (uint32_t B = t; B < PG.n_super; B += kRunThreads)
+                reinterpret_cast<uint4 *>(table)[(size_t)B * PG.n_sub + s] = reinterpret_cast<const uint4 *>(cnt)[B];
+        } else {
+            const uint16_t *starts = reinterpret_cast<const uint16_t *>(cnt);
+            for (uint32_t b = t; b < PG.n_slices; b += kRunThreads)
+                table[((size_t)(b / PG.sub) * PG.n_sub + s) * PG.sub + b % PG.sub] = starts[b];
+        }
+        if (t == 0) table[((size_t)PG.n_super * PG.n_sub + s) * PG.sub] = (uint16_t)total;
+        __syncthreads();
+
+        {
+            auto place = [&](uint32_t p, uint32_t host) {
+                const uint32_t b = p >> PG.sl, sh16 = (b & 1u) << 4;
+                const uint32_t slot = (atomicAdd(&cnt[b >> 1], 1u << sh16) >> sh16) & 0xFFFFu;
+                sorted[slot] = (host << PG.sl) | (p & mask);
+            };
+            uint32_t host = host_t, i = i_t;
+#pragma unroll
+            for (uint32_t j = 0; j < kRunPerThread; ++j) {
+                if (j < jfull || (j == jfull && t < tail)) place(pid[j], host);
+                const bool wrap = i + PG.dr >= G.g;
+                i = i + PG.dr - (wrap ? G.g : 0u);
+                host += PG.dq + (wrap ? 1u : 0u);
+            }
+        }
+        __syncthreads();
+        uint4 *out = reinterpret_cast<uint4 *>(entries + (size_t)s * PG.region);
+        for (uint32_t q = t; q < total / 4; q += kRunThreads) out[q] = reinterpret_cast<const uint4 *>(sorted)[q];
+        // Ready the next subgroup: the copy above reads only the sorted entries.
+        for (uint32_t q = t; q < nsp; q += kRunThreads) cnt[q] = 0;
+        if (t < nh_next) keys[t] = host_key(G, aip_next);
+        __syncthreads();
     }
-    __syncthreads();
-    uint4 *out = reinterpret_cast<uint4 *>(entries + (size_t)s * PG.region);
-    for (uint32_t q = t; q < total / 4; q += kRunThreads) out[q] = reinterpret_cast<const uint4 *>(sorted)[q];
 }
 
 // ---------------------------------------------------------------------------
