@@ -488,7 +488,11 @@ __global__ void __launch_bounds__(kFinThreads) k_run_finalize(Geo G, PartGeo PG,
 
 // The learned estimate (window k) from packed histogram rows: per wavefront
 // 16 hosts' features, the network on the matrix cores, exp of its output
-// (the closed form where that is not finite).
+// (the closed form where that is not finite).  The 16 rows are contiguous in
+// memory and are staged in LDS with one coalesced pass; live counts and
+// features are then read from there.
+constexpr uint32_t kLearnedRowp = (VATE_MLP_FEATURES - 3 + 2) / 2;   // rowp at the largest learned k
+
 __global__ void __launch_bounds__(256) k_learned_rows(Geo G, const DevState *__restrict__ st, uint32_t n,
                                                      uint32_t rowp, const uint32_t *__restrict__ rows,
                                                      const float *__restrict__ cf, const mlp::Packed *__restrict__ P,
@@ -496,33 +500,39 @@ __global__ void __launch_bounds__(256) k_learned_rows(Geo G, const DevState *__r
 {
     __shared__ __attribute__((aligned(16))) uint16_t xs_all[4][16 * mlp::LDS_STRIDE];
     __shared__ __attribute__((aligned(16))) uint16_t a1_all[4][16 * mlp::LDS_STRIDE];
+    __shared__ uint32_t rows_all[4][16 * kLearnedRowp];
     __shared__ float cf_w[4][16];
     __shared__ uint32_t live_w[4][16];
+    if (rowp > kLearnedRowp) return;   // k beyond the network's inputs: rejected by the entry points
     const uint64_t active_pool = pool_active(st, G.k);
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63, q = l >> 4, c = l & 15;
     const uint32_t h0 = blockIdx.x * 64 + 16 * w;
+    const uint32_t nh = h0 < n ? min(16u, n - h0) : 0u;
     const float fg = (float)G.g, occupancy = (float)active_pool / (float)G.N;
+    uint32_t *rw = rows_all[w];
+    {
+        const uint32_t *src = rows + (size_t)h0 * rowp;
+        for (uint32_t e = l; e < nh * rowp; e += 64) rw[e] = src[e];
+        if (l < 16) cf_w[w][l] = (uint32_t)l < nh ? cf[h0 + l] : 0.f;
+    }
+    __syncthreads();
     if (l < 16) {
-        const uint32_t h = h0 + l;
         uint32_t live = 0;
-        float v = 0.f;
-        if (h < n) {
-            const uint32_t *row = rows + (size_t)h * rowp;
-            for (uint32_t d = 0; d < G.k; ++d) live += hist_bin(row, d);
-            v = cf[h];
+        if ((uint32_t)l < nh) {
+            const uint32_t *row = rw + l * rowp;
+            for (uint32_t j = 0; j < G.k / 2; ++j) live += (row[j] & 0xFFFFu) + (row[j] >> 16);   // bins 2j, 2j+1 < k
+            if (G.k & 1u) live += row[G.k / 2] & 0xFFFFu;                                      // bin k - 1
         }
         live_w[w][l] = live;
-        cf_w[w][l] = v;
     }
     __syncthreads();
     uint16_t *xs = xs_all[w];
     for (int e = l; e < 16 * VATE_MLP_FEATURES; e += 64) {
         const int m = e >> 6, f = e & 63;
-        const uint32_t h = h0 + m;
         float x = 0.f;
-        if (h < n) {
+        if ((uint32_t)m < nh) {
             if (f < (int)G.k)
-                x = (float)hist_bin(rows + (size_t)h * rowp, f) / fg;
+                x = (float)hist_bin(rw + m * rowp, f) / fg;
             else if (f == (int)G.k)
                 x = (float)live_w[w][m] / fg;
             else if (f == (int)G.k + 1)
@@ -540,10 +550,10 @@ __global__ void __launch_bounds__(256) k_learned_rows(Geo G, const DevState *__r
     float a2v[4][4], o4[4];
     mlp::forward16(P, xs, a1_all[w], r4, z1, z2, a2v, o4);
     if (c < 4) {
-        const uint32_t h = h0 + 4 * q + c;
-        if (h < n) {
+        const uint32_t m = 4 * q + c;
+        if (m < nh) {
             const float ex = expf(o4[c]);
-            est[h] = isfinite(ex) ? ex : cf_w[w][4 * q + c];
+            est[h0 + m] = isfinite(ex) ? ex : cf_w[w][m];
         }
     }
 }
