@@ -913,10 +913,10 @@ static bool part_geo(const vate_sketch *s, uint64_t n, PartGeo *out)
     // Hosts per subgroup: the largest count whose VATs fit the scatter's
     // registers, whose padded sorted entries (+ slice counters, keys) fit its
     // LDS, and whose histograms fit the finalize's LDS.
-    const uint64_t nsp = (((ns + 1) >> 1) + 3) & ~3ull;
-    auto lds_for = [&](uint64_t hosts) {
+    const uint64_t nsp = (ns + 3) & ~3ull;
+    auto lds_for = [&](uint64_t hosts) {   // counters, keys, 16-bit sort slots
         const uint64_t cap = (hosts * G.g + 3 * ns + 3) & ~3ull;
-        return 4 * (nsp + ((hosts + 3) & ~3ull) + cap);
+        return 4 * (nsp + ((hosts + 3) & ~3ull)) + 2 * cap;
     };
     uint64_t hosts = kRunMaxHosts;
     hosts = std::min<uint64_t>(hosts, kRunMaxEntries / G.g);
@@ -932,6 +932,7 @@ static bool part_geo(const vate_sketch *s, uint64_t n, PartGeo *out)
     p.dq = kRunThreads / G.g;
     p.dr = kRunThreads % G.g;
     p.fast = G.a >= (1ull << sl) ? 1u : 0u;
+    p.gmul = G.g == 1 ? 0u : (uint32_t)(((1ull << 32) + G.g - 1) / G.g);
     p.lds_scatter = (uint32_t)lds_for(hosts);
     p.lds_lookup = (uint32_t)(((((uint64_t)w << sl) >> 3) + 15) & ~15ull);
     p.lds_final = p.hosts * p.rowp * 4u;

@@ -6,14 +6,17 @@
 // The direct gather reads one random cache line per VAT anywhere in the
 // pool, so it is bound by line fills from beyond L2.  Here:
 //
-//  k_run_scatter  one workgroup per subgroup of hosts.  Hashes the
-//                 subgroup's VATs once (pids stay in registers), counts them
-//                 per pool slice in LDS, places them by an LDS counting sort
-//                 and copies the sorted entries (host within subgroup, AT
-//                 within slice) to the workspace as one coalesced stream.
-//                 Every (subgroup, slice) run starts on a 4-entry boundary
-//                 (padded with kRunPad), so no 16-byte chunk is shared by two
-//                 slices.  Run starts go to a u16 table laid out
+//  k_run_scatter  persistent workgroups, one subgroup of hosts at a time.
+//                 Hashes the subgroup's VATs (their slices stay in
+//                 registers), counts them per pool slice in LDS, places their
+//                 16-bit indices by an LDS counting sort (two bytes a slot is
+//                 what lets a subgroup hold 63 hosts of g = 1024), then
+//                 copies the sorted entries (host within subgroup, AT within
+//                 slice; the pid hashed again from the index) to the
+//                 workspace as one coalesced stream.  Every (subgroup, slice)
+//                 run starts on a 4-entry boundary (padded with kRunPad), so
+//                 no 16-byte chunk is shared by two slices.  Run starts, in
+//                 chunks, go to a u16 table laid out
 //                 [super-slice][subgroup][slice in super].
 //  k_run_lookup   one workgroup per pool slice (128 KiB of ATs, held in LDS).
 //                 Walks that slice's run in every subgroup and writes, beside
@@ -31,8 +34,9 @@
 // written and read back once.
 
 constexpr uint32_t kRunThreads = 1024;                          // scatter / lookup workgroup
-constexpr uint32_t kRunPerThread = 32;                          // VATs hashed per scatter thread
-constexpr uint32_t kRunMaxEntries = kRunThreads * kRunPerThread; // VATs per subgroup
+constexpr uint32_t kRunPerThread = 64;                          // VATs hashed per scatter thread
+constexpr uint32_t kRunMaxEntries = 65535;                      // VATs per subgroup: 16-bit indices, one value spare
+constexpr uint32_t kSortPad = 0xFFFFu;                          // padding slot of the LDS sort
 constexpr uint32_t kRunLdsMax = 160u * 1024u;                   // gfx950 LDS per workgroup
 constexpr uint32_t kRunLdsStatic = 64u;                         // k_run_scatter's static LDS (wsum)
 constexpr uint32_t kSliceBytesLog2 = 17;                        // pool bytes per slice: 128 KiB
@@ -42,6 +46,9 @@ constexpr uint32_t kRunPad = 0xFFFFFFFFu;                       // padding entry
 constexpr uint32_t kSuper = 8;                                  // slices per super-slice
 constexpr uint32_t kFinThreads = 256;
 constexpr uint32_t kLookupSplit = 2;                            // subgroup ranges per slice (lookup)
+constexpr uint32_t kLanesPerRun = 16;                           // lookup lanes per run, one 16-byte chunk each
+constexpr uint32_t kRunsPerStep = 64 / kLanesPerRun;            // runs per wavefront step
+constexpr uint32_t kSubPerWave = 8 * kRunsPerStep;              // subgroups per wavefront per pipeline stage
 constexpr uint32_t kFinHistBytes = 64u * 1024u;                 // per-subgroup histogram ceiling
 
 struct PartGeo {
@@ -62,6 +69,7 @@ struct PartGeo {
     uint32_t span;        // subgroups per range (a multiple of 1024)
     uint32_t lds_scatter, lds_lookup, lds_final;
     uint32_t dbits;       // distance bits of a result: values 0..k, all ones = padding
+    uint32_t gmul;        // ceil(2^32 / g), v / g = umulhi(v, gmul) for v < 2^16; 0 for g = 1
 };
 
 // ---------------------------------------------------------------------------
@@ -73,12 +81,11 @@ __global__ void __launch_bounds__(kRunThreads) k_run_scatter(Geo G, PartGeo PG, 
 {
     extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
     __shared__ uint32_t wsum[kRunThreads / 64];
-    const uint32_t nwords = (PG.n_slices + 1u) >> 1;       // two 16-bit counters per word
-    const uint32_t nsp = (nwords + 3u) & ~3u;
+    const uint32_t nsp = (PG.n_slices + 3u) & ~3u;
     const uint32_t nkp = (PG.hosts + 3u) & ~3u;
-    uint32_t *cnt = lds;                  // slice counts, then cursors (16-bit pairs)
+    uint32_t *cnt = lds;                  // per-slice counts, then cursors
     uint32_t *keys = lds + nsp;           // host keys
-    uint32_t *sorted = keys + nkp;        // entries sorted by slice, runs padded to 4
+    uint16_t *sorted = reinterpret_cast<uint16_t *>(keys + nkp);   // VAT indices by slice, runs padded to 4
     const uint32_t t = threadIdx.x;
     const uint32_t mask = (1u << PG.sl) - 1u;
     const uint32_t host_t0 = t / G.g, i_t0 = t - host_t0 * G.g;
@@ -102,39 +109,30 @@ __global__ void __launch_bounds__(kRunThreads) k_run_scatter(Geo G, PartGeo PG, 
         const uint32_t nh_next = sn < PG.n_sub ? min(PG.hosts, n - sn * PG.hosts) : 0u;
         uint32_t aip_next = 0;
         if (t < nh_next) aip_next = hosts[(size_t)sn * PG.hosts + t];
-        // Opaque per iteration, so the compiler does not hoist the 32 VATs'
-        // LDS addresses out of the loop (they would not fit in registers).
+        // Opaque per iteration, so the compiler does not hoist the VATs' LDS
+        // addresses out of the loop (they would not fit in registers).
         uint32_t host_t = host_t0, i_t = i_t0;
         asm volatile("" : "+v"(host_t), "+v"(i_t));
 
-        // VAT v = t + j * kRunThreads is VAT i = v mod g of host v / g.  H's
-        // multiplier i * phi is carried along (mod 2^32); when g divides the
-        // workgroup size, i (and i * phi) stay fixed and only the host advances.
-        // Iterations j < jfull are full for every thread (a uniform branch); the
-        // ragged tail is iteration jfull.  H(aip, i) = top c bits of the mix
-        // (shift = 32 - c is at most 31).
+        // VAT v = t + j * kRunThreads of the subgroup is VAT i = v mod g of
+        // host v / g.  H's multiplier i * phi is carried along (mod 2^32);
+        // when g divides the workgroup size, i (and i * phi) stay fixed and
+        // only the host advances.  Iterations j < jfull are full for every
+        // thread (a uniform branch); the ragged tail is iteration jfull.
+        // H(aip, i) = top c bits of the mix (shift = 32 - c is at most 31).
         const uint32_t jfull = nv / kRunThreads, tail = nv - jfull * kRunThreads;
-        uint32_t pid[kRunPerThread];
-        if (PG.dr == 0 && G.blog == 0) {
+        uint32_t bs[kRunPerThread / 2];    // slices of the thread's VATs, two 16-bit values per word
+#pragma unroll
+        for (uint32_t j = 0; j < kRunPerThread / 2; ++j) bs[j] = 0;
+        if (PG.dr == 0) {
             const uint32_t ik = i_t * kPhi;
 #pragma unroll
             for (uint32_t j = 0; j < kRunPerThread; ++j) {
                 const uint32_t host = host_t + j * PG.dq;
                 if (j < jfull || (j == jfull && t < tail)) {
-                    pid[j] = mix(keys[host] ^ ik) >> G.shift;
-                    const uint32_t b = pid[j] >> PG.sl;
-                    atomicAdd(&cnt[b >> 1], 1u << ((b & 1u) << 4));
-                }
-            }
-        } else if (PG.dr == 0) {                 // locality-blocked H, i fixed
-            const uint32_t bm = (1u << G.blog) - 1u, ikb = (i_t >> G.blog) * kPhi, low = i_t & bm;
-#pragma unroll
-            for (uint32_t j = 0; j < kRunPerThread; ++j) {
-                const uint32_t host = host_t + j * PG.dq;
-                if (j < jfull || (j == jfull && t < tail)) {
-                    pid[j] = ((mix(keys[host] ^ ikb) >> G.shift) & ~bm) | low;
-                    const uint32_t b = pid[j] >> PG.sl;
-                    atomicAdd(&cnt[b >> 1], 1u << ((b & 1u) << 4));
+                    const uint32_t b = (mix(keys[host] ^ ik) >> G.shift) >> PG.sl;
+                    bs[j >> 1] |= b << ((j & 1u) << 4);
+                    atomicAdd(&cnt[b], 1u);
                 }
             }
         } else {
@@ -142,9 +140,9 @@ __global__ void __launch_bounds__(kRunThreads) k_run_scatter(Geo G, PartGeo PG, 
 #pragma unroll
             for (uint32_t j = 0; j < kRunPerThread; ++j) {
                 if (j < jfull || (j == jfull && t < tail)) {
-                    pid[j] = G.blog ? vat_pid(G, keys[host], i) : mix(keys[host] ^ ik) >> G.shift;
-                    const uint32_t b = pid[j] >> PG.sl;
-                    atomicAdd(&cnt[b >> 1], 1u << ((b & 1u) << 4));
+                    const uint32_t b = (mix(keys[host] ^ ik) >> G.shift) >> PG.sl;
+                    bs[j >> 1] |= b << ((j & 1u) << 4);
+                    atomicAdd(&cnt[b], 1u);
                 }
                 const bool wrap = i + PG.dr >= G.g;
                 i = i + PG.dr - (wrap ? G.g : 0u);
@@ -154,16 +152,14 @@ __global__ void __launch_bounds__(kRunThreads) k_run_scatter(Geo G, PartGeo PG, 
         }
         __syncthreads();
 
-        // Exclusive scan of the padded slice counts; thread t owns whole counter
-        // words [t pw, (t+1) pw), i.e. slices [2 t pw, 2 (t+1) pw).
-        const uint32_t pw = (nwords + kRunThreads - 1) / kRunThreads;
-        const uint32_t w0 = t * pw;
+        // Exclusive scan of the padded slice counts; thread t owns slices
+        // [t ps, (t+1) ps).  Run starts become the cursors, padding slots
+        // are marked.
+        const uint32_t ps = (PG.n_slices + kRunThreads - 1) / kRunThreads;
+        const uint32_t b0 = t * ps;
         uint32_t mine = 0;
-        for (uint32_t q = 0; q < pw; ++q)
-            if (w0 + q < nwords) {
-                const uint32_t v = cnt[w0 + q];
-                mine += pad4(v & 0xFFFFu) + pad4(v >> 16);
-            }
+        for (uint32_t q = 0; q < ps; ++q)
+            if (b0 + q < PG.n_slices) mine += pad4(cnt[b0 + q]);
         const uint32_t lane = t & 63u, wv = t >> 6;
         uint32_t incl = mine;
 #pragma unroll
@@ -175,52 +171,61 @@ __global__ void __launch_bounds__(kRunThreads) k_run_scatter(Geo G, PartGeo PG, 
         __syncthreads();
         uint32_t run = incl - mine;
         for (uint32_t q = 0; q < wv; ++q) run += wsum[q];
-        for (uint32_t q = 0; q < pw; ++q) {
-            const uint32_t w = w0 + q;
-            if (w >= nwords) break;
-            const uint32_t v = cnt[w], c0 = v & 0xFFFFu, c1 = v >> 16;
-            const uint32_t p0 = run, p1 = run + pad4(c0);
-            run = p1 + pad4(c1);
-            cnt[w] = p0 | (p1 << 16);
-            for (uint32_t x = p0 + c0; x < p1; ++x) sorted[x] = kRunPad;
-            for (uint32_t x = p1 + c1; x < run; ++x) sorted[x] = kRunPad;
+        for (uint32_t q = 0; q < ps; ++q) {
+            const uint32_t b = b0 + q;
+            if (b >= PG.n_slices) break;
+            const uint32_t c = cnt[b], p = run;
+            run += pad4(c);
+            cnt[b] = p;
+            for (uint32_t x = p + c; x < run; ++x) sorted[x] = kSortPad;
         }
         uint32_t total = 0;
         for (uint32_t q = 0; q < kRunThreads / 64; ++q) total += wsum[q];
         __syncthreads();
-        // Run starts to the table, one (super-slice, subgroup) cell per store:
-        // the cursor words are the starts as little-endian u16, slice by slice.
+        // Run starts to the table in 4-entry chunks, one 16-byte
+        // (super-slice, subgroup) cell per store.
         if (PG.sub == kSuper) {
-            for (uint32_t B = t; B < PG.n_super; B += kRunThreads)
-                reinterpret_cast<uint4 *>(table)[(size_t)B * PG.n_sub + s] = reinterpret_cast<const uint4 *>(cnt)[B];
+            for (uint32_t B = t; B < PG.n_super; B += kRunThreads) {
+                const uint32_t *c8 = cnt + 8u * B;
+                reinterpret_cast<uint4 *>(table)[(size_t)B * PG.n_sub + s] =
+                    make_uint4((c8[0] >> 2) | ((c8[1] >> 2) << 16), (c8[2] >> 2) | ((c8[3] >> 2) << 16),
+                               (c8[4] >> 2) | ((c8[5] >> 2) << 16), (c8[6] >> 2) | ((c8[7] >> 2) << 16));
+            }
         } else {
-            const uint16_t *starts = reinterpret_cast<const uint16_t *>(cnt);
             for (uint32_t b = t; b < PG.n_slices; b += kRunThreads)
-                table[((size_t)(b / PG.sub) * PG.n_sub + s) * PG.sub + b % PG.sub] = starts[b];
+                table[((size_t)(b / PG.sub) * PG.n_sub + s) * PG.sub + b % PG.sub] = (uint16_t)(cnt[b] >> 2);
         }
-        if (t == 0) table[((size_t)PG.n_super * PG.n_sub + s) * PG.sub] = (uint16_t)total;
+        if (t == 0) table[((size_t)PG.n_super * PG.n_sub + s) * PG.sub] = (uint16_t)(total >> 2);
         __syncthreads();
 
-        {
-            auto place = [&](uint32_t p, uint32_t host) {
-                const uint32_t b = p >> PG.sl, sh16 = (b & 1u) << 4;
-                const uint32_t slot = (atomicAdd(&cnt[b >> 1], 1u << sh16) >> sh16) & 0xFFFFu;
-                sorted[slot] = (host << PG.sl) | (p & mask);
-            };
-            uint32_t host = host_t, i = i_t;
 #pragma unroll
-            for (uint32_t j = 0; j < kRunPerThread; ++j) {
-                if (j < jfull || (j == jfull && t < tail)) place(pid[j], host);
-                const bool wrap = i + PG.dr >= G.g;
-                i = i + PG.dr - (wrap ? G.g : 0u);
-                host += PG.dq + (wrap ? 1u : 0u);
+        for (uint32_t j = 0; j < kRunPerThread; ++j)
+            if (j < jfull || (j == jfull && t < tail)) {
+                const uint32_t slot = atomicAdd(&cnt[(bs[j >> 1] >> ((j & 1u) << 4)) & 0xFFFFu], 1u);
+                sorted[slot] = (uint16_t)(t + j * kRunThreads);
             }
-        }
         __syncthreads();
+
+        // Copy out, one 4-entry chunk per thread and step: each VAT index
+        // becomes its entry (host within subgroup, AT within slice), its pid
+        // hashed again (v / g by a multiply-high: exact for v, g < 2^16).
         uint4 *out = reinterpret_cast<uint4 *>(entries + (size_t)s * PG.region);
-        for (uint32_t q = t; q < total / 4; q += kRunThreads) out[q] = reinterpret_cast<const uint4 *>(sorted)[q];
-        // Ready the next subgroup: the copy above reads only the sorted entries.
+        for (uint32_t q = t; q < total / 4; q += kRunThreads) {
+            const uint2 v2 = reinterpret_cast<const uint2 *>(sorted)[q];
+            const uint32_t v[4] = {v2.x & 0xFFFFu, v2.x >> 16, v2.y & 0xFFFFu, v2.y >> 16};
+            uint32_t e[4];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const uint32_t host = PG.gmul ? __umulhi(v[m], PG.gmul) : v[m], i = v[m] - host * G.g;
+                const uint32_t pid_m = mix(keys[min(host, PG.hosts - 1u)] ^ (i * kPhi)) >> G.shift;
+                e[m] = v[m] == kSortPad ? kRunPad : (host << PG.sl) | (pid_m & mask);
+            }
+            out[q] = make_uint4(e[0], e[1], e[2], e[3]);
+        }
+        // Ready the next subgroup: the copy above reads only the sorted
+        // indices and the keys, so both wait for the barrier.
         for (uint32_t q = t; q < nsp; q += kRunThreads) cnt[q] = 0;
+        __syncthreads();
         if (t < nh_next) keys[t] = host_key(G, aip_next);
         __syncthreads();
     }
@@ -298,13 +303,14 @@ __global__ void __launch_bounds__(kRunThreads) k_run_lookup(Geo G, PartGeo PG, c
         return d < G.k ? d : G.k;
     };
 
-    // Eight lanes per subgroup run, four entries (one 16-byte chunk) per lane.
-    // A wavefront takes 64 subgroups at a time: one coalesced read of their
-    // run bounds, then the first chunk of eight runs per lane group is loaded
-    // before any is used (eight independent loads in flight per lane); the
-    // rare chunks beyond a run's first eight follow in a second pass.
+    // kLanesPerRun lanes per subgroup run, four entries (one 16-byte chunk)
+    // per lane.  A wavefront takes kSubPerWave subgroups at a time: one
+    // coalesced read of their run bounds, then the first chunk of eight runs
+    // per lane group is loaded before any is used (eight independent loads in
+    // flight per lane); the rare chunks beyond a run's first kLanesPerRun
+    // follow in a second pass.
     const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
-    const uint32_t grp = lane >> 3, gl = lane & 7u;
+    const uint32_t grp = lane / kLanesPerRun, gl = lane % kLanesPerRun;
     const size_t row = (size_t)B * PG.n_sub, next_row = (size_t)(B + 1) * PG.n_sub;
     // Runs start and end on 4-entry boundaries: every chunk belongs to one
     // run.  A padding entry's result is all ones.
@@ -321,7 +327,7 @@ __global__ void __launch_bounds__(kRunThreads) k_run_lookup(Geo G, PartGeo PG, c
     // are already in flight.
     auto bounds = [&](uint32_t s0, uint32_t &st_l, uint32_t &en_l) {
         st_l = en_l = 0;
-        if (s0 + lane < s_hi) {
+        if (lane < kSubPerWave && s0 + lane < s_hi) {
             const size_t cell = (row + s0 + lane) * PG.sub;
             st_l = table[cell + j];
             en_l = j + 1 < PG.sub ? table[cell + j + 1] : table[(next_row + s0 + lane) * PG.sub];
@@ -330,33 +336,35 @@ __global__ void __launch_bounds__(kRunThreads) k_run_lookup(Geo G, PartGeo PG, c
     auto issue = [&](uint32_t s0, uint32_t st_l, uint32_t en_l, uint4 e4[8]) {
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-            const uint32_t start = __shfl(st_l, 8 * q + (int)grp, 64), end = __shfl(en_l, 8 * q + (int)grp, 64);
-            const uint32_t c = (start >> 2) + gl;
+            const uint32_t r = kRunsPerStep * q + grp;
+            const uint32_t start = __shfl(st_l, (int)r, 64), end = __shfl(en_l, (int)r, 64);
+            const uint32_t c = start + gl;
             e4[q] = make_uint4(0u, 0u, 0u, 0u);
-            if (c < (end >> 2))
-                e4[q] = reinterpret_cast<const uint4 *>(entries + (size_t)(s0 + 8 * q + grp) * PG.region)[c];
+            if (c < end) e4[q] = reinterpret_cast<const uint4 *>(entries + (size_t)(s0 + r) * PG.region)[c];
         }
     };
     auto finish = [&](uint32_t s0, uint32_t st_l, uint32_t en_l, const uint4 e4[8]) {
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-            const uint32_t start = __shfl(st_l, 8 * q + (int)grp, 64), end = __shfl(en_l, 8 * q + (int)grp, 64);
-            const uint32_t c = (start >> 2) + gl;
-            if (c < (end >> 2)) resolve(s0 + 8 * q + grp, c, e4[q]);
+            const uint32_t r = kRunsPerStep * q + grp;
+            const uint32_t start = __shfl(st_l, (int)r, 64), end = __shfl(en_l, (int)r, 64);
+            const uint32_t c = start + gl;
+            if (c < end) resolve(s0 + r, c, e4[q]);
         }
-        for (int q = 0; q < 8; ++q) {      // chunks beyond a run's first eight
-            const uint32_t start = __shfl(st_l, 8 * q + (int)grp, 64), end = __shfl(en_l, 8 * q + (int)grp, 64);
-            const uint32_t s = s0 + 8 * q + grp, c1 = end >> 2;
+        for (int q = 0; q < 8; ++q) {      // chunks beyond a run's first kLanesPerRun
+            const uint32_t r = kRunsPerStep * q + grp;
+            const uint32_t start = __shfl(st_l, (int)r, 64), end = __shfl(en_l, (int)r, 64);
+            const uint32_t s = s0 + r, c1 = end;
             const uint4 *ent = reinterpret_cast<const uint4 *>(entries + (size_t)s * PG.region);
-            for (uint32_t c = (start >> 2) + 8u + gl;; c += 8u) {
+            for (uint32_t c = start + kLanesPerRun + gl;; c += kLanesPerRun) {
                 const bool act = c < c1;
                 if (!__ballot(act)) break;
                 if (act) resolve(s, c, ent[c]);
             }
         }
     };
-    const uint32_t step = kRunThreads;            // 16 wavefronts x 64 subgroups
-    uint32_t s0 = s_lo + wv * 64u;
+    const uint32_t step = (kRunThreads / 64) * kSubPerWave;   // 16 wavefronts
+    uint32_t s0 = s_lo + wv * kSubPerWave;
     uint32_t stA, enA, stB, enB;
     uint4 eA[8];
     bounds(s0, stA, enA);
@@ -405,7 +413,7 @@ __global__ void __launch_bounds__(kFinThreads) k_run_finalize(Geo G, PartGeo PG,
     const uint32_t s = blockIdx.x, t = threadIdx.x;
     const uint32_t h0 = s * PG.hosts;
     const uint32_t nh = min(PG.hosts, n - h0);
-    const uint32_t nvp = table[((size_t)PG.n_super * PG.n_sub + s) * PG.sub];   // padded entries
+    const uint32_t nvp = 4u * table[((size_t)PG.n_super * PG.n_sub + s) * PG.sub];   // padded entries
     const uint32_t rowp = PG.rowp;
     for (uint32_t q = t; q < nh * rowp; q += kFinThreads) hist[q] = 0;
     __syncthreads();
