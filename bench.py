@@ -348,7 +348,7 @@ def main() -> int:
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                 "traffic_source": traffic_src,
-                "kernel": "estimate phase: k_run_scatter + k_run_lookup<8> + k_run_finalize + k_learned_rows",
+                "kernel": "estimate phase: k_run_scatter + k_run_lookup<8> + k_run_finalize<learned>",
                 "algorithmic_bytes_per_launch": bytes_per_host * pop.n_hosts,
                 "avg_launch_ms": est_ms,
                 "traffic_gbs": traffic / (est_ms * 1e-3) / 1e9 if traffic else None,

@@ -83,13 +83,14 @@ int vate_estimate_learned(vate_sketch *s, const uint32_t *hosts_dev, size_t n_ho
                           const void *weights_dev, float *est_dev, float *est_cf_dev,
                           void *stream);
 
-/* Workspace (bytes) for vate_estimate_learned_ws with n_hosts hosts: that of
- * vate_estimate_ws plus one packed 16-bit (k+1)-bin histogram row per host. */
+/* Workspace (bytes) for vate_estimate_learned_ws with n_hosts hosts: the
+ * same as vate_estimate_ws needs (the network runs on the histograms while
+ * they are in LDS). */
 int vate_estimate_learned_workspace_bytes(const vate_sketch *s, size_t n_hosts, size_t *bytes);
 
 /* Same outputs as vate_estimate_learned, with the VAT lookups of
  * vate_estimate_ws (grouped by pool slice, resolved in LDS) and the network
- * applied per 16-host tile afterwards.  workspace_dev: 256-byte aligned, at
+ * applied per 16-host tile in the pass that builds the histograms.  workspace_dev: 256-byte aligned, at
  * least vate_estimate_learned_workspace_bytes; caller-owned scratch. */
 int vate_estimate_learned_ws(vate_sketch *s, const uint32_t *hosts_dev, size_t n_hosts,
                              const void *weights_dev, float *est_dev, float *est_cf_dev,

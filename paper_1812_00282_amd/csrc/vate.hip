@@ -953,11 +953,10 @@ struct RunWs {
     uint16_t *res;              // [n_sub][region] lookup results: host within subgroup, distance
     uint16_t *table;            // [n_super + 1][n_sub][sub] run starts
     unsigned long long *cum;    // [k + 1] census prefix (several windows)
-    uint32_t *rows;             // [n_sub 2^sh][rowp] packed histograms (learned estimate)
     size_t bytes;
 };
 
-static RunWs run_ws(const PartGeo &pg, uint32_t k, void *base, bool learned = false)
+static RunWs run_ws(const PartGeo &pg, uint32_t k, void *base)
 {
     RunWs w;
     const uintptr_t p = reinterpret_cast<uintptr_t>(base);
@@ -971,8 +970,6 @@ static RunWs run_ws(const PartGeo &pg, uint32_t k, void *base, bool learned = fa
     off += align256((size_t)(pg.n_super + 1) * pg.n_sub * pg.sub * 2);
     w.cum = reinterpret_cast<unsigned long long *>(p + off);
     off += align256((size_t)(k + 1) * 8);
-    w.rows = reinterpret_cast<uint32_t *>(p + off);
-    if (learned) off += align256((size_t)pg.n_sub * pg.hosts * pg.rowp * 4);
     w.bytes = off;
     return w;
 }
@@ -1003,7 +1000,7 @@ static int launch_part(vate_sketch *s, const PartGeo &pg, void *ws, const uint32
         if (rc != VATE_OK) return rc;
         attr = true;
     }
-    const RunWs w = run_ws(pg, s->p.k, ws, MODE == kFinLearned);
+    const RunWs w = run_ws(pg, s->p.k, ws);
     if (steps != PART_RUN)
         k_run_scatter<<<std::min(pg.n_sub, s->n_cu), kRunThreads, pg.lds_scatter, st>>>(s->G, pg, hosts, n, w.entries,
                                                                                        w.table);
@@ -1012,11 +1009,8 @@ static int launch_part(vate_sketch *s, const PartGeo &pg, void *ws, const uint32
                                                                                   w.table, w.res);
     if (MODE == kFinMulti) k_census_prefix<<<1, 64, 0, st>>>(s->G, s->st, w.cum);
     k_run_finalize<MODE><<<pg.n_sub, kFinThreads, pg.lds_final, st>>>(
-        s->G, pg, s->st, n, kprime, w.res, w.table, est, live, MODE == kFinLearned ? w.rows : hist, win, w.cum,
+        s->G, pg, s->st, n, kprime, w.res, w.table, est, live, hist, win, w.cum,
         static_cast<const mlp::Packed *>(weights), cf);
-    if (MODE == kFinLearned)
-        k_learned_rows<<<(n + 63) / 64, 256, 0, st>>>(s->G, s->st, n, pg.rowp, w.rows, cf,
-                                                       static_cast<const mlp::Packed *>(weights), est);
     return VATE_OK;
 }
 
@@ -1372,7 +1366,7 @@ int vate_estimate_learned_workspace_bytes(const vate_sketch *s, size_t n_hosts, 
     if (!s || !bytes) return VATE_E_INVAL;
     if (n_hosts > 0xFFFFFFFFull - 1024) return VATE_E_INVAL;
     PartGeo pg;
-    *bytes = part_geo(s, n_hosts, &pg) ? run_ws(pg, s->p.k, nullptr, true).bytes : 256;
+    *bytes = part_geo(s, n_hosts, &pg) ? run_ws(pg, s->p.k, nullptr).bytes : 256;
     return VATE_OK;
 }
 

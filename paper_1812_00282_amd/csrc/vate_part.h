@@ -398,6 +398,48 @@ __device__ __forceinline__ uint32_t hist_bin(const uint32_t *row, uint32_t d)
     return (row[d >> 1] >> ((d & 1u) << 4)) & 0xFFFFu;
 }
 
+// The learned estimate (window k) of n16 <= 16 hosts by one whole wavefront:
+// features from their packed histogram rows (LDS, stride rowp), live counts
+// and closed forms (LDS, 16 each), the network on the matrix cores, exp of
+// its output (the closed form where that is not finite) to est[0, n16).
+// Every wavefront of the workgroup calls it (the network has a barrier).
+__device__ __forceinline__ void learned16(const Geo &G, float occupancy, const uint32_t *rw, uint32_t rowp,
+                                          uint32_t n16, const float *cf16, const uint32_t *live16, uint16_t *xs,
+                                          uint16_t *a1, const mlp::Packed *__restrict__ P, float *__restrict__ est)
+{
+    const int l = threadIdx.x & 63, q = l >> 4, c = l & 15;
+    const float fg = (float)G.g;
+    for (int e = l; e < 16 * VATE_MLP_FEATURES; e += 64) {
+        const int m = e >> 6, f = e & 63;
+        float x = 0.f;
+        if ((uint32_t)m < n16) {
+            if (f < (int)G.k)
+                x = (float)hist_bin(rw + m * rowp, f) / fg;
+            else if (f == (int)G.k)
+                x = (float)live16[m] / fg;
+            else if (f == (int)G.k + 1)
+                x = occupancy;
+            else if (f == (int)G.k + 2)
+                x = logf(fmaxf(cf16[m], 1.0f)) * 0.0625f;
+        }
+        xs[m * mlp::LDS_STRIDE + f] = mlp::bf16_bits(x);
+    }
+    __syncthreads();
+    float r4[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) r4[r] = logf(fmaxf(cf16[4 * q + r], 1.0f));
+    mlp::f32x4 z1[4], z2[4];
+    float a2v[4][4], o4[4];
+    mlp::forward16(P, xs, a1, r4, z1, z2, a2v, o4);
+    if (c < 4) {
+        const uint32_t m = 4 * q + c;
+        if (m < n16) {
+            const float ex = expf(o4[c]);
+            est[m] = isfinite(ex) ? ex : cf16[m];
+        }
+    }
+}
+
 template <int MODE>
 __global__ void __launch_bounds__(kFinThreads) k_run_finalize(Geo G, PartGeo PG, const DevState *__restrict__ st,
                                                              uint32_t n, uint32_t kprime,
@@ -479,89 +521,39 @@ __global__ void __launch_bounds__(kFinThreads) k_run_finalize(Geo G, PartGeo PG,
             }
         }
     } else {
-        // Learned estimate: the closed form for window k and the packed
-        // histogram rows go out; the network runs in k_learned_rows, which
-        // keeps this streaming pass free of the network's register demand.
+        // Learned estimate, in groups of 64 hosts (16 per wavefront): the
+        // closed form for window k, then the network fed from the LDS rows.
+        __shared__ __attribute__((aligned(16))) uint16_t xs_all[kFinThreads / 64][16 * mlp::LDS_STRIDE];
+        __shared__ __attribute__((aligned(16))) uint16_t a1_all[kFinThreads / 64][16 * mlp::LDS_STRIDE];
+        __shared__ float cf_s[kFinThreads / 4];
+        __shared__ uint32_t live_s[kFinThreads / 4];
         const uint64_t active_pool = pool_active(st, G.k);
-        for (uint32_t h = t; h < nh; h += kFinThreads) {
-            const uint32_t *row = hist + h * rowp;
-            uint32_t live = 0;
-            for (uint32_t d = 0; d < G.k; ++d) live += hist_bin(row, d);
-            cf_out[h0 + h] = estimate_from_counts(G.g - live, G.N - active_pool, G.g, G.c);
-        }
-        uint32_t *out = hist_out + (size_t)h0 * rowp;
-        for (uint32_t q = t; q < nh * rowp; q += kFinThreads) out[q] = hist[q];
-    }
-}
-
-// The learned estimate (window k) from packed histogram rows: per wavefront
-// 16 hosts' features, the network on the matrix cores, exp of its output
-// (the closed form where that is not finite).  The 16 rows are contiguous in
-// memory and are staged in LDS with one coalesced pass; live counts and
-// features are then read from there.
-constexpr uint32_t kLearnedRowp = (VATE_MLP_FEATURES - 3 + 2) / 2;   // rowp at the largest learned k
-
-__global__ void __launch_bounds__(256) k_learned_rows(Geo G, const DevState *__restrict__ st, uint32_t n,
-                                                     uint32_t rowp, const uint32_t *__restrict__ rows,
-                                                     const float *__restrict__ cf, const mlp::Packed *__restrict__ P,
-                                                     float *__restrict__ est)
-{
-    __shared__ __attribute__((aligned(16))) uint16_t xs_all[4][16 * mlp::LDS_STRIDE];
-    __shared__ __attribute__((aligned(16))) uint16_t a1_all[4][16 * mlp::LDS_STRIDE];
-    __shared__ uint32_t rows_all[4][16 * kLearnedRowp];
-    __shared__ float cf_w[4][16];
-    __shared__ uint32_t live_w[4][16];
-    if (rowp > kLearnedRowp) return;   // k beyond the network's inputs: rejected by the entry points
-    const uint64_t active_pool = pool_active(st, G.k);
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63, q = l >> 4, c = l & 15;
-    const uint32_t h0 = blockIdx.x * 64 + 16 * w;
-    const uint32_t nh = h0 < n ? min(16u, n - h0) : 0u;
-    const float fg = (float)G.g, occupancy = (float)active_pool / (float)G.N;
-    uint32_t *rw = rows_all[w];
-    {
-        const uint32_t *src = rows + (size_t)h0 * rowp;
-        for (uint32_t e = l; e < nh * rowp; e += 64) rw[e] = src[e];
-        if (l < 16) cf_w[w][l] = (uint32_t)l < nh ? cf[h0 + l] : 0.f;
-    }
-    __syncthreads();
-    if (l < 16) {
-        uint32_t live = 0;
-        if ((uint32_t)l < nh) {
-            const uint32_t *row = rw + l * rowp;
-            for (uint32_t j = 0; j < G.k / 2; ++j) live += (row[j] & 0xFFFFu) + (row[j] >> 16);   // bins 2j, 2j+1 < k
-            if (G.k & 1u) live += row[G.k / 2] & 0xFFFFu;                                      // bin k - 1
-        }
-        live_w[w][l] = live;
-    }
-    __syncthreads();
-    uint16_t *xs = xs_all[w];
-    for (int e = l; e < 16 * VATE_MLP_FEATURES; e += 64) {
-        const int m = e >> 6, f = e & 63;
-        float x = 0.f;
-        if ((uint32_t)m < nh) {
-            if (f < (int)G.k)
-                x = (float)hist_bin(rw + m * rowp, f) / fg;
-            else if (f == (int)G.k)
-                x = (float)live_w[w][m] / fg;
-            else if (f == (int)G.k + 1)
-                x = occupancy;
-            else if (f == (int)G.k + 2)
-                x = logf(fmaxf(cf_w[w][m], 1.0f)) * 0.0625f;
-        }
-        xs[m * mlp::LDS_STRIDE + f] = mlp::bf16_bits(x);
-    }
-    __syncthreads();
-    float r4[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) r4[r] = logf(fmaxf(cf_w[w][4 * q + r], 1.0f));
-    mlp::f32x4 z1[4], z2[4];
-    float a2v[4][4], o4[4];
-    mlp::forward16(P, xs, a1_all[w], r4, z1, z2, a2v, o4);
-    if (c < 4) {
-        const uint32_t m = 4 * q + c;
-        if (m < nh) {
-            const float ex = expf(o4[c]);
-            est[h0 + m] = isfinite(ex) ? ex : cf_w[w][m];
+        const float occupancy = (float)active_pool / (float)G.N;
+        const uint32_t w = t >> 6;
+        for (uint32_t base = 0; base < nh; base += kFinThreads / 4) {
+            if (t < kFinThreads / 4) {
+                uint32_t live = 0;
+                float cf = 0.f;
+                if (base + t < nh) {
+                    const uint32_t *row = hist + (base + t) * rowp;
+                    for (uint32_t j = 0; j < G.k / 2; ++j) live += (row[j] & 0xFFFFu) + (row[j] >> 16);
+                    if (G.k & 1u) live += row[G.k / 2] & 0xFFFFu;
+                    cf = estimate_from_counts(G.g - live, G.N - active_pool, G.g, G.c);
+                    cf_out[h0 + base + t] = cf;
+                }
+                cf_s[t] = cf;
+                live_s[t] = live;
+            }
+            __syncthreads();
+            const uint32_t m0 = base + 16 * w;
+            const uint32_t n16 = nh > m0 ? min(16u, nh - m0) : 0u;
+            // Opaque per group, so the weight fragments are loaded where they
+            // are used rather than hoisted out of the loop into registers.
+            const mlp::Packed *Pg = P;
+            asm volatile("" : "+s"(Pg));
+            learned16(G, occupancy, hist + m0 * rowp, rowp, n16, cf_s + 16 * w, live_s + 16 * w, xs_all[w],
+                      a1_all[w], Pg, est + h0 + m0);
+            __syncthreads();
         }
     }
 }

@@ -395,6 +395,9 @@ def test_multi_window_estimates(w, k, c):
     (18, 8, 5, 3, 0, 2500),         # g = 3
     (23, 7, 60, 1024, 0, 300),      # exact 7-bit ATs, 64 slices of 2^17
     (21, 10, 300, 512, 1, 500),     # exact 10-bit ATs (slices of 2^16), 16-bit distances
+    (20, 8, 12, 100, 0, 200_000),   # 655 hosts per subgroup, 306 subgroups: persistent scatter
+                                    # workgroups take two each, ragged last one, v / g by multiply-high
+    (24, 8, 60, 1024, 0, 20_000),   # 63 hosts per subgroup (the 16-bit sort's limit), 318 subgroups
 ])
 def test_partitioned_geometries(c, w, k, g, partition, n_hosts):
     """The partitioned lookups across their geometry cases: live counts,
