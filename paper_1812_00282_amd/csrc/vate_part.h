@@ -25,10 +25,13 @@
 //                 window k).  The 8 slices of a super-slice are given
 //                 to one XCD: their runs are adjacent in memory, so the lines
 //                 they read and the distance bytes they write meet in that
-//                 XCD's L2.
+//                 XCD's L2.  Each slice's walk is split over kLookupSplit
+//                 workgroups (ranges of subgroups).
 //  k_run_finalize one workgroup per subgroup.  Streams the results back,
 //                 builds each host's distance histogram in LDS and forms
-//                 Eq. 11 for k', several windows, or the learned estimate.
+//                 Eq. 11 for k', several windows, or the learned estimate
+//                 (the network fed from the LDS histograms, 16 hosts per
+//                 wavefront).
 //
 // HBM traffic per VAT: 4 B entry written and read back once, 2 B result
 // written and read back once.
