@@ -354,7 +354,10 @@ __global__ void __launch_bounds__(kRunThreads) k_run_lookup(Geo G, PartGeo PG, c
             const uint32_t c = start + gl;
             if (c < end) resolve(s0 + r, c, e4[q]);
         }
-        for (int q = 0; q < 8; ++q) {      // chunks beyond a run's first kLanesPerRun
+        // Chunks beyond a run's first kLanesPerRun, when any run of the
+        // group has them (rare: runs average about a third of that).
+        if (!__ballot(en_l - st_l > kLanesPerRun)) return;
+        for (int q = 0; q < 8; ++q) {
             const uint32_t r = kRunsPerStep * q + grp;
             const uint32_t start = __shfl(st_l, (int)r, 64), end = __shfl(en_l, (int)r, 64);
             const uint32_t s = s0 + r, c1 = end;
