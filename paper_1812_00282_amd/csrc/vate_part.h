@@ -468,7 +468,7 @@ __global__ void __launch_bounds__(kFinThreads) k_run_finalize(Geo G, PartGeo PG,
     {
         const uint4 *rr = reinterpret_cast<const uint4 *>(res + (size_t)s * PG.region);   // 8 results per load
         const uint32_t dmask = (1u << PG.dbits) - 1u;
-        constexpr uint32_t U = 4;     // loads in flight per thread
+        constexpr uint32_t U = 8;     // loads in flight per thread
         const uint32_t nch = (nvp + 7u) >> 3;     // nvp is a multiple of 4
         for (uint32_t c0 = t; c0 < nch; c0 += U * kFinThreads) {
             uint4 r4[U];
