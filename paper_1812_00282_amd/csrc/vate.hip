@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <type_traits>
 #include <cstdio>
 #include <cstring>
@@ -990,15 +991,20 @@ static int launch_part(vate_sketch *s, const PartGeo &pg, void *ws, const uint32
                        uint32_t kprime, float *est, uint32_t *live, uint32_t *hist, const Windows &win,
                        const void *weights, float *cf, hipStream_t st, int steps = PART_ALL)
 {
-    static bool attr = false;
-    if (!attr) {
+    // The dynamic-LDS limits are a per-device function attribute: set once
+    // per device (bit d of the mask) and instantiation.
+    static std::atomic<uint64_t> attr_set{0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+    const uint64_t bit = 1ull << (dev & 63);
+    if (!(attr_set.load(std::memory_order_acquire) & bit)) {
         int rc = set_lds_limit(s, reinterpret_cast<const void *>(&k_run_scatter), s->lds_budget);
         if (rc == VATE_OK)
             rc = set_lds_limit(s, reinterpret_cast<const void *>(&k_run_lookup<W>), 1u << kSliceBytesLog2);
         if (rc == VATE_OK)
             rc = set_lds_limit(s, reinterpret_cast<const void *>(&k_run_finalize<MODE>), kFinHistBytes);
         if (rc != VATE_OK) return rc;
-        attr = true;
+        attr_set.fetch_or(bit, std::memory_order_release);
     }
     const RunWs w = run_ws(pg, s->p.k, ws);
     if (steps != PART_RUN)
