@@ -908,7 +908,10 @@ static bool part_geo(const vate_sketch *s, uint64_t n, PartGeo *out)
     p.sub = p.n_slices < kSuper ? p.n_slices : kSuper;
     p.n_super = p.n_slices / p.sub;
     p.xcd = p.n_super >= 8 ? 1u : 0u;
-    p.rowp = (G.k + 2u) / 2u;
+    // Histogram rows of ceil((k+1)/2) words, made odd: most of a host's VATs
+    // land in its bin k, and an odd stride puts those bins of different hosts
+    // in different LDS banks (an even stride maps them onto few banks).
+    p.rowp = ((G.k + 2u) / 2u) | 1u;
     p.dbits = 1;                                        // distances 0..k and an all-ones padding mark
     while ((1u << p.dbits) - 1u <= G.k) ++p.dbits;
     // Hosts per subgroup: the largest count whose VATs fit the scatter's

@@ -66,7 +66,7 @@ struct PartGeo {
     uint32_t region;      // entries between subgroup regions (cap rounded up to 64)
     uint32_t dq, dr;      // kRunThreads = dq * g + dr
     uint32_t fast;        // every block holds >= 2^sl ATs: a slice meets at most two blocks
-    uint32_t rowp;        // u32 words per packed 16-bit histogram row, ceil((k + 1) / 2)
+    uint32_t rowp;        // u32 words per packed 16-bit histogram row: ceil((k + 1) / 2), made odd
     uint32_t xcd;         // map the slices of a super-slice to one XCD
     uint32_t split;       // lookup workgroups per slice, each over a range of subgroups
     uint32_t span;        // subgroups per range (a multiple of 1024)
