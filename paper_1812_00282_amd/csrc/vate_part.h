@@ -485,13 +485,28 @@ __global__ void __launch_bounds__(kFinThreads) k_run_finalize(Geo G, PartGeo PG,
 #pragma unroll
                 for (int m = 0; m < 8; ++m) {
                     if (8u * c + m >= nvp) break;
+                    // Bin k (inactive for window k, most of the VATs) and
+                    // padding (d all ones) are not counted: bin k is g minus
+                    // the others, filled in below.
                     const uint32_t r = (w[m >> 1] >> ((m & 1) << 4)) & 0xFFFFu;
                     const uint32_t d = r & dmask;
-                    if (d == dmask) continue;
-                    const uint32_t dm = min(d, G.k);
-                    atomicAdd(&hist[(r >> PG.dbits) * rowp + (dm >> 1)], 1u << ((dm & 1u) << 4));
+                    if (d >= G.k) continue;
+                    atomicAdd(&hist[(r >> PG.dbits) * rowp + (d >> 1)], 1u << ((d & 1u) << 4));
                 }
             }
+        }
+    }
+    __syncthreads();
+    for (uint32_t h = t; h < nh; h += kFinThreads) {   // bin k = g - (bins 0 .. k-1)
+        uint32_t *row = hist + h * rowp;
+        uint32_t live = 0;
+        for (uint32_t j = 0; j < G.k / 2; ++j) live += (row[j] & 0xFFFFu) + (row[j] >> 16);
+        const uint32_t w = G.k >> 1;
+        if (G.k & 1u) {
+            live += row[w] & 0xFFFFu;
+            row[w] = (row[w] & 0xFFFFu) | ((G.g - live) << 16);
+        } else {
+            row[w] = G.g - live;
         }
     }
     __syncthreads();
