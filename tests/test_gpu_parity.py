@@ -6,6 +6,7 @@ are bit-exact; FP32 estimates agree with the oracle's FP64 values within
 oracle's own cancellation error in g ln Z_p - g ln Z_v (each logarithm is at
 most 32 ln 2 in magnitude, so its double rounding error is below 2^-47).
 """
+import ctypes
 import math
 
 import numpy as np
@@ -171,8 +172,17 @@ def test_ragged_inputs_and_alignment():
     _check_state(gpu, ref, "ragged")
     for n in (0, 1, 63, 64, 65, 255, 256, 257, 599):
         if n == 0:
-            est, _, _ = gpu.estimate(hosts[:0])
-            assert est.numel() == 0
+            for part in (False, True):
+                est, _, _ = gpu.estimate(hosts[:0], partitioned=part)
+                assert est.numel() == 0
+            # the C entry points themselves: no hosts is a no-op, a plan of
+            # no hosts is refused
+            lib = _lib.lib()
+            kps = (ctypes.c_uint32 * 1)(cfg.k)
+            assert lib.vate_estimate_ws(gpu.handle, None, 0, cfg.k, None, None, None, None, 0, None) == 0
+            assert lib.vate_estimate_multi_ws(gpu.handle, None, 0, kps, 1, None, None, 0, None) == 0
+            assert lib.vate_estimate_learned_ws(gpu.handle, None, 0, None, None, None, None, 0, None) == 0
+            assert lib.vate_estimate_plan(gpu.handle, None, 0, None, 0, None) == _lib.VATE_E_INVAL
             continue
         _check_estimates(gpu, ref, hosts[:n], hist=True, what=f"{n} hosts")
 
