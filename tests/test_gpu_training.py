@@ -57,3 +57,6 @@ def test_committed_network_beats_closed_form(bg):
     print(res)
     assert res["all"]["learned"] <= res["all"]["closed_form_clamped"]
     assert res["all"]["learned"] <= res["all"]["closed_form"]
+    # the buckets where the closed form is weakest: small and saturating hosts
+    for b in ("[1,100)", "[5000,inf)"):
+        assert res[b]["learned"] < res[b]["closed_form_clamped"], b
