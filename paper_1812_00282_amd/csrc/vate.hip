@@ -914,9 +914,10 @@ static bool part_geo(const vate_sketch *s, uint64_t n, PartGeo *out)
     p.rowp = ((G.k + 2u) / 2u) | 1u;
     p.dbits = 1;                                        // distances 0..k and an all-ones padding mark
     while ((1u << p.dbits) - 1u <= G.k) ++p.dbits;
-    // Hosts per subgroup: the largest count whose VATs fit the scatter's
-    // registers, whose padded sorted entries (+ slice counters, keys) fit its
-    // LDS, and whose histograms fit the finalize's LDS.
+    // Hosts per subgroup: the largest count whose VATs have 16-bit indices
+    // (the scatter's sort slots and registers hold at most 65,535), whose
+    // padded sort (+ slice counters, keys) fits its LDS, whose histograms fit
+    // the finalize's LDS, and whose host index fits a 16-bit result.
     const uint64_t nsp = (ns + 3) & ~3ull;
     auto lds_for = [&](uint64_t hosts) {   // counters, keys, 16-bit sort slots
         const uint64_t cap = (hosts * G.g + 3 * ns + 3) & ~3ull;
