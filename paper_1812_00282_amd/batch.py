@@ -11,7 +11,6 @@ import ctypes
 import json
 import os
 
-import numpy as np
 import torch
 
 from ._lib import VateBatchTune, VateError, lib

@@ -12,7 +12,6 @@ from dataclasses import dataclass
 import numpy as np
 import torch
 
-from . import _lib
 from ._lib import VateParams, check, lib
 
 

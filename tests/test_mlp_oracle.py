@@ -1,5 +1,4 @@
 """Pins of the learned-estimator CPU oracle (oracle/mlp_ref.py).  CPU only."""
-import math
 
 import numpy as np
 import pytest
