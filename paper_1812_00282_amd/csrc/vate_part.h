@@ -446,8 +446,11 @@ __device__ __forceinline__ void learned16(const Geo &G, float occupancy, const u
     }
 }
 
+// At least 5 wavefronts per SIMD: the network's registers would otherwise
+// hold the streaming pass to 4 (measured 0.64 against 0.58 ms on the 40G
+// workload; 6 would spill).
 template <int MODE>
-__global__ void __launch_bounds__(kFinThreads) k_run_finalize(Geo G, PartGeo PG, const DevState *__restrict__ st,
+__global__ void __launch_bounds__(kFinThreads, 5) k_run_finalize(Geo G, PartGeo PG, const DevState *__restrict__ st,
                                                              uint32_t n, uint32_t kprime,
                                                              const uint16_t *__restrict__ res,
                                                              const uint16_t *__restrict__ table, float *__restrict__ est,
