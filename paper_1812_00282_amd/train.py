@@ -191,8 +191,8 @@ def load(path: str = WEIGHTS, device="cuda") -> torch.Tensor:
 
 def main() -> int:
     ap = argparse.ArgumentParser()
-    ap.add_argument("--states", type=int, default=10_000_000)
-    ap.add_argument("--epochs", type=int, default=240)
+    ap.add_argument("--states", type=int, default=20_000_000)
+    ap.add_argument("--epochs", type=int, default=120)
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--lr", type=float, default=3e-3)
     ap.add_argument("--out", default=WEIGHTS)
