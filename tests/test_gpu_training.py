@@ -49,7 +49,7 @@ def test_training_beats_closed_form_on_held_out(bg):
 
 def test_committed_network_beats_closed_form(bg):
     """The committed network (trained by python -m paper_1812_00282_amd.train
-    on 10M states) against the closed form on the held-out seeds 50-59."""
+    on 20M states) against the closed form on the held-out seeds 50-59."""
     assert os.path.exists(T.WEIGHTS), "trained weights are missing"
     theta = T.load()
     held = T.generate(T.HELD_OUT_SEEDS[:4], bg)
