@@ -410,6 +410,7 @@ def test_multi_window_estimates(w, k, c):
     (24, 8, 60, 1024, 0, 20_000),   # 63 hosts per subgroup (the 16-bit sort's limit), 318 subgroups
     (22, 4, 7, 100, 1, 200_000),    # 4-bit ATs, low-deviation partition, 306 subgroups
     (21, 16, 129, 64, 0, 100_000),  # 16-bit ATs, 252 hosts per subgroup, 397 subgroups
+    (23, 10, 300, 256, 0, 50_000),  # exact 10-bit ATs, 108 hosts per subgroup, 463 subgroups
 ])
 def test_partitioned_geometries(c, w, k, g, partition, n_hosts):
     """The partitioned lookups across their geometry cases: live counts,
