@@ -162,6 +162,24 @@ int vate_estimate_ws(vate_sketch *s, const uint32_t *hosts_dev, size_t n_hosts,
                      uint32_t kprime, float *est_dev, uint32_t *live_dev, uint32_t *hist_dev,
                      void *workspace_dev, size_t workspace_bytes, void *stream);
 
+/* vate_estimate_ws for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the workspace is a fixed array of VATE_NOALLOC_SCRATCH_BYTES
+ * in device memory that the library holds on every GPU it runs on, from
+ * module load until the process ends.  No call allocates or frees anything.
+ * Same arguments (minus the workspace), outputs, layouts and results as
+ * vate_estimate_ws.  Every call on one GPU shares that GPU's array, which
+ * keeps the last call's contents: calls that overlap on one GPU (from any
+ * sketch, stream or host thread) race and must not be issued.  The host
+ * count is limited by the array: at g = 1024 about 10,000 hosts.
+ * Errors: as vate_estimate_ws; VATE_E_INVAL when the host count needs more
+ * workspace than VATE_NOALLOC_SCRATCH_BYTES (vate_estimate_workspace_bytes
+ * tells); VATE_E_DEVICE if the array's device address cannot be found. */
+#define VATE_NOALLOC_SCRATCH_BYTES (64u << 20)
+int vate_estimate_noalloc(vate_sketch *s, const uint32_t *hosts_dev, size_t n_hosts,
+                          uint32_t kprime, float *est_dev, uint32_t *live_dev,
+                          uint32_t *hist_dev, void *stream);
+
 /* vate_estimate_ws in two parts, for a host list that stays the same from
  * slice to slice (the monitored hosts of Alg. 4's ANet): the VAT addresses
  * depend only on the hosts and H, not on the pool, so

@@ -55,6 +55,7 @@ _SIGS = {
     "vate_read_census": (_i32, [_vp, _vp, _vp]),
     "vate_estimate_workspace_bytes": (_i32, [_vp, _sz, ctypes.POINTER(_sz)]),
     "vate_estimate_ws": (_i32, [_vp, _vp, _sz, _u32, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "vate_estimate_noalloc": (_i32, [_vp, _vp, _sz, _u32, _vp, _vp, _vp, _vp]),
     "vate_estimate_plan": (_i32, [_vp, _vp, _sz, _vp, _sz, _vp]),
     "vate_estimate_run": (_i32, [_vp, _sz, _u32, _vp, _vp, _vp, _vp, _sz, _vp]),
     "vate_estimate_multi_workspace_bytes": (_i32, [_vp, _sz, ctypes.POINTER(_sz)]),
@@ -108,6 +109,7 @@ MLP_FEATURES = 64
 MLP_HIDDEN = 64
 MLP_PARAMS = 8385
 MLP_WEIGHT_BYTES = 25600
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 _lib = None
 

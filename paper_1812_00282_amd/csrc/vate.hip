@@ -1168,11 +1168,14 @@ int vate_estimate_workspace_bytes(const vate_sketch *s, size_t n_hosts, size_t *
     return VATE_OK;
 }
 
-int vate_estimate_ws(vate_sketch *s, const uint32_t *hosts_dev, size_t n_hosts, uint32_t kprime, float *est_dev,
-                     uint32_t *live_dev, uint32_t *hist_dev, void *workspace_dev, size_t workspace_bytes,
-                     void *stream)
+}  // extern "C"
+
+// vate_estimate_ws and vate_estimate_noalloc: the same checks and launches;
+// `what` names the entry point in error messages.
+static int estimate_ws_impl(vate_sketch *s, const uint32_t *hosts_dev, size_t n_hosts, uint32_t kprime,
+                            float *est_dev, uint32_t *live_dev, uint32_t *hist_dev, void *workspace_dev,
+                            size_t workspace_bytes, hipStream_t st, const char *what)
 {
-    if (!s) return VATE_E_INVAL;
     if (s->dead) return VATE_E_DEVICE;
     if (!s->closed) return fail(s, VATE_E_STATE, "estimate needs a closed slice (call vate_close_slice)");
     if (kprime < 1 || kprime > s->p.k) return fail(s, VATE_E_INVAL, "k' must be in [1, k]");
@@ -1186,7 +1189,6 @@ int vate_estimate_ws(vate_sketch *s, const uint32_t *hosts_dev, size_t n_hosts, 
         (reinterpret_cast<uintptr_t>(est_dev) & 3u) || (reinterpret_cast<uintptr_t>(live_dev) & 3u) ||
         (reinterpret_cast<uintptr_t>(hist_dev) & 3u))
         return fail(s, VATE_E_INVAL, "hosts/est/live/hist must be non-NULL (live, hist may be NULL) and 4-byte aligned");
-    hipStream_t st = static_cast<hipStream_t>(stream);
     const uint32_t n = (uint32_t)n_hosts;
     PartGeo pg;
     if (!part_geo(s, n, &pg)) {      // outside the partitioned limits: direct gather
@@ -1195,12 +1197,72 @@ int vate_estimate_ws(vate_sketch *s, const uint32_t *hosts_dev, size_t n_hosts, 
         by_width(s->p.width, [&](auto W) {
             launch_estimate<decltype(W)::value>(s, hosts_dev, n, kprime, est_dev, live_dev, hist_dev, st);
         });
-        return check_launch(s, "estimate_ws");
+        return check_launch(s, what);
     }
     const int rc = launch_part_w<kFinClosedForm>(s, pg, workspace_dev, hosts_dev, n, kprime, est_dev, live_dev,
                                                  hist_dev, Windows{}, nullptr, nullptr, st);
     if (rc != VATE_OK) return rc;
-    return check_launch(s, "estimate_ws");
+    return check_launch(s, what);
+}
+
+// Workspace of vate_estimate_noalloc: a fixed array in device memory.  Each
+// GPU the library runs on holds its own copy from module load until the
+// process ends.  Host code never uses the array's name as a device address
+// (on the host it names a stand-in): the address is looked up once per
+// device with hipGetSymbolAddress, and that pointer is what the launches get.
+static __device__ __align__(256) uint8_t scratch[VATE_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+static std::atomic<void *> g_scratch_dev[kMaxDevices];
+
+// Device address of the current device's scratch array (looked up on the
+// first call per device), or null with the HIP error in *err.
+static void *scratch_address(hipError_t *err)
+{
+    int dev = 0;
+    *err = hipGetDevice(&dev);
+    if (*err != hipSuccess) return nullptr;
+    if (dev < 0 || dev >= kMaxDevices) {
+        *err = hipErrorInvalidDevice;
+        return nullptr;
+    }
+    void *p = g_scratch_dev[dev].load(std::memory_order_acquire);
+    if (p) return p;
+    *err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (*err != hipSuccess) return nullptr;
+    g_scratch_dev[dev].store(p, std::memory_order_release);
+    return p;
+}
+
+extern "C" {
+int vate_estimate_ws(vate_sketch *s, const uint32_t *hosts_dev, size_t n_hosts, uint32_t kprime, float *est_dev,
+                     uint32_t *live_dev, uint32_t *hist_dev, void *workspace_dev, size_t workspace_bytes,
+                     void *stream)
+{
+    if (!s) return VATE_E_INVAL;
+    return estimate_ws_impl(s, hosts_dev, n_hosts, kprime, est_dev, live_dev, hist_dev, workspace_dev,
+                            workspace_bytes, static_cast<hipStream_t>(stream), "estimate_ws");
+}
+
+int vate_estimate_noalloc(vate_sketch *s, const uint32_t *hosts_dev, size_t n_hosts, uint32_t kprime,
+                          float *est_dev, uint32_t *live_dev, uint32_t *hist_dev, void *stream)
+{
+    if (!s) return VATE_E_INVAL;
+    if (s->dead) return VATE_E_DEVICE;
+    size_t need = 0;
+    if (n_hosts > 0xFFFFFFFFull - 1024) return fail(s, VATE_E_INVAL, "too many hosts");
+    vate_estimate_workspace_bytes(s, n_hosts, &need);
+    if (need > VATE_NOALLOC_SCRATCH_BYTES) {
+        char buf[200];
+        snprintf(buf, sizeof(buf), "estimate_noalloc: %zu hosts need %zu bytes of workspace, more than the %u of the "
+                 "fixed scratch (use vate_estimate_ws)", n_hosts, need, (unsigned)VATE_NOALLOC_SCRATCH_BYTES);
+        return fail(s, VATE_E_INVAL, buf);
+    }
+    hipError_t e = hipSuccess;
+    void *ws = scratch_address(&e);
+    if (!ws) return fail(s, VATE_E_DEVICE, hipGetErrorString(e));
+    return estimate_ws_impl(s, hosts_dev, n_hosts, kprime, est_dev, live_dev, hist_dev, ws,
+                            VATE_NOALLOC_SCRATCH_BYTES, static_cast<hipStream_t>(stream), "estimate_noalloc");
 }
 
 int vate_estimate_plan(vate_sketch *s, const uint32_t *hosts_dev, size_t n_hosts, void *workspace_dev,
