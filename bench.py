@@ -65,46 +65,150 @@ def measured_traffic(path=None):
     return None, None
 
 
-def cpu_baseline(wl, pop, slices, budget_hosts: int = 20_000) -> dict:
-    """The CPU oracle, single-threaded, on a bounded sample of the same
-    workload: one slice of ingest (5M packets), the pool scan behind Z_p,
-    and the estimation of `budget_hosts` hosts, scaled to a whole slice
-    (all hosts), reported in packets/s."""
-    from oracle.vate_ref import OracleSketch, lib
+def cpu_info() -> dict:
+    """Host cores this process may use and the CPU model (from /proc/cpuinfo)."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.lower().startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return {"nproc": usable, "cpu_count": os.cpu_count(), "model": model}
 
+
+def _oracle_estimate_worker(ref, k, hosts, conn) -> None:
+    """One all-core worker: the Z_p scan alone, then the oracle's estimate of
+    its shard (which scans again); the difference is the per-host work."""
+    t0 = time.perf_counter()
+    ref.pool_inactive(k)
+    t1 = time.perf_counter()
+    ref.estimate(hosts, want_live=False)
+    t2 = time.perf_counter()
+    conn.send((t1 - t0, t2 - t1))
+    conn.close()
+
+
+def cpu_baseline(wl, pop, slices, sample_hosts: int = 4096, measured: int = 4,
+                 max_workers: int = 16) -> dict:
+    """The CPU oracle on the same stream, in steady state: k untimed slices
+    fill the window, then `measured` slices are timed phase by phase -
+    PT (advance + preservation of the due blocks), ST (ingest of the slice's
+    packets) and ET (the pool scan behind Z_p plus the per-host estimate,
+    timed on `sample_hosts` hosts per slice and scaled to all hosts).  An
+    all-core leg then forks worker processes from the same oracle state and
+    shards a larger host sample over them (each worker runs the oracle's
+    unchanged estimate, its own Z_p scan included).  Reported in packets/s
+    per whole slice (ST + PT + ET for every host)."""
+    import multiprocessing as mp
+
+    from oracle.vate_ref import OracleSketch
+
+    info = cpu_info()
     ref = OracleSketch(wl.log2_pool, wl.width, wl.k, wl.g, 0xA5A5, 0x5A5A)
+    n = len(slices)
     t0 = time.perf_counter()
-    ref.ingest(slices[0])
-    t_ingest = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    ref.close_slice()
-    t_close = time.perf_counter() - t0
+    for s in range(wl.k):
+        ref.ingest(slices[s % n])
+        ref.close_slice()
+    t_fill = time.perf_counter() - t0
+    log(f"[bench] cpu oracle: window filled ({wl.k} slices, {t_fill:.1f} s)")
+    empty = np.zeros((0, 2), dtype=np.uint32)
+    rng = np.random.default_rng(12345)
+    st, pt, et_call = [], [], []
+    for j in range(measured):
+        s = wl.k + j
+        t0 = time.perf_counter()
+        ref.ingest(empty)                 # the closed slice advances: BACT0, t, Alg. 3
+        t1 = time.perf_counter()
+        ref.ingest(slices[s % n])         # SetAT for every packet
+        t2 = time.perf_counter()
+        ref.close_slice()
+        hosts = pop.aips[rng.choice(pop.n_hosts, size=sample_hosts, replace=False)]
+        t3 = time.perf_counter()
+        ref.estimate(hosts, want_live=False)
+        t4 = time.perf_counter()
+        pt.append(t1 - t0)
+        st.append(t2 - t1)
+        et_call.append(t4 - t3)
+        log(f"[bench] cpu oracle: slice {s} PT {pt[-1]:.3f} s, ST {st[-1]:.3f} s, "
+            f"estimate of {sample_hosts} hosts {et_call[-1]:.2f} s")
     t0 = time.perf_counter()
     ref.pool_inactive(wl.k)
     t_scan = time.perf_counter() - t0
-    hosts = pop.aips[:budget_hosts]
+    per_host = max(float(np.mean(et_call)) - t_scan, 0.0) / sample_hosts
+    st_s, pt_s = float(np.mean(st)), float(np.mean(pt))
+    et_s = t_scan + per_host * pop.n_hosts
+    slice_1 = st_s + pt_s + et_s
+
+    # all-core leg: workers forked from this oracle state, each estimating a
+    # shard of the host sample (fork: the 512 MiB pool is shared copy-on-write)
+    workers = max(1, min(max_workers, info["nproc"]))
+    shard = 4 * sample_hosts
+    hosts = pop.aips[rng.choice(pop.n_hosts, size=workers * shard, replace=False)]
+    ctx = mp.get_context("fork")
+    procs, pipes = [], []
     t0 = time.perf_counter()
-    ref.estimate(hosts, want_live=False)
-    t_est = time.perf_counter() - t0
-    per_host = max(t_est - t_scan, 0.0) / hosts.size
-    # preservation of the two due blocks happens in the next close/ingest
-    t0 = time.perf_counter()
-    ref.close_slice()
-    t_adv = time.perf_counter() - t0
-    slice_s = t_ingest + t_close + t_scan + per_host * pop.n_hosts + t_adv
-    del lib
+    for w in range(workers):
+        a, b = ctx.Pipe(duplex=False)
+        p = ctx.Process(target=_oracle_estimate_worker,
+                        args=(ref, wl.k, hosts[w * shard:(w + 1) * shard], b))
+        p.start()
+        procs.append(p)
+        pipes.append(a)
+    worker_s = [c.recv() for c in pipes]
+    for p in procs:
+        p.join()
+    wall = time.perf_counter() - t0
+    # per-host work of each worker: its estimate minus its own Z_p scan
+    busy = max(max(e - z for z, e in worker_s), 1e-9)
+    per_host_all = busy / (workers * shard)
+    et_all = t_scan + per_host_all * pop.n_hosts
+    slice_all = st_s + pt_s + et_all
+    log(f"[bench] cpu oracle: all-core estimate, {workers} workers x {shard} hosts, {wall:.2f} s")
     return {
-        "value": wl.packets_per_slice / slice_s,
+        "value": wl.packets_per_slice / slice_all,
         "unit": "packets/s",
-        "cores": 1,
+        "cores": workers,
         "kind": "oracle",
-        "sample": (f"one slice of the same stream: ingest {wl.packets_per_slice} packets, "
-                   f"one Z_p pool scan, estimate {hosts.size} of {pop.n_hosts} hosts "
-                   f"(scaled to all), one advance+preserve; "
-                   f"ingest {t_ingest:.2f}s, scan {t_scan:.2f}s, "
-                   f"{per_host * 1e6:.1f}us/host, advance {t_adv:.3f}s"),
-        "hosts_per_s": 1.0 / per_host if per_host > 0 else None,
+        "sample": (f"the same stream in steady state: {wl.k} untimed slices fill the window, then "
+                   f"{measured} slices timed per phase (PT advance+preserve, ST ingest of "
+                   f"{wl.packets_per_slice} packets, ET = one Z_p pool scan + {sample_hosts} sampled "
+                   f"hosts per slice scaled to all {pop.n_hosts}); value uses ET from the all-core leg "
+                   f"({workers} forked workers x {shard} hosts; one Z_p scan + the hosts at the "
+                   f"workers' combined rate), ST and PT single-threaded"),
+        "cpu": info,
+        "per_slice_s": {"ST": st_s, "PT": pt_s, "ET_one_core": et_s, "ET_all_cores": et_all,
+                        "Z_p_scan": t_scan},
+        "one_core": {"packets_per_s": wl.packets_per_slice / slice_1, "hosts_per_s": 1.0 / per_host,
+                     "slice_s": slice_1},
+        "all_cores": {"workers": workers, "packets_per_s": wl.packets_per_slice / slice_all,
+                      "hosts_per_s": 1.0 / per_host_all, "slice_s": slice_all,
+                      "worker_scan_and_estimate_s": [[round(z, 3), round(e, 3)] for z, e in worker_s]},
+        "slices_timed": [wl.k, wl.k + measured - 1],
     }
+
+
+def _gen_slice(args):
+    wl, pop, s = args
+    return wl.slice(pop, s)
+
+
+def generate_slices(wl, pop, n: int) -> list:
+    """The workload's first n slices (numpy, seeded per slice), drawn by
+    forked worker processes (before the GPU is touched)."""
+    import multiprocessing as mp
+
+    workers = max(1, min(16, cpu_info()["nproc"], n))
+    if workers == 1:
+        return [wl.slice(pop, s) for s in range(n)]
+    with mp.get_context("fork").Pool(workers) as pool:
+        return pool.map(_gen_slice, [(wl, pop, s) for s in range(n)])
 
 
 def batched_leg(dev, n_slices: int = 8) -> dict:
@@ -244,10 +348,15 @@ def main() -> int:
     from paper_1812_00282_amd.sketch import Config, Sketch
 
     wl = streams.LINK40G
-    n_gen = min(wl.n_slices, args.warmup + args.steps)
+    n_gen = wl.n_slices
     log(f"[bench] generating {n_gen} slices of {wl.name}")
     pop = wl.population()
-    host_slices = [wl.slice(pop, s) for s in range(n_gen)]
+    host_slices = generate_slices(wl, pop, n_gen)
+    cpu = None
+    if not args.no_cpu_baseline:
+        # before the GPU is touched: the all-core leg forks worker processes
+        log("[bench] cpu baseline (oracle)")
+        cpu = cpu_baseline(wl, pop, host_slices)
     dev = torch.device("cuda:0")
     slices = [torch.from_numpy(s.view(np.int32)).to(dev) for s in host_slices]
     hosts = torch.from_numpy(pop.aips.view(np.int32)).to(dev)
@@ -286,16 +395,20 @@ def main() -> int:
         torch.cuda.synchronize()
         log("[bench] calibration copy of 1 GiB done")
         del src, dst
-    log(f"[bench] warmup {args.warmup}")
-    for s in range(args.warmup):
+    # steady state: the window of k slices fills before anything is timed
+    # (2k untimed slices, cycling the generated ones), whatever --warmup is
+    preroll = 2 * wl.k
+    log(f"[bench] pre-roll {preroll} slices, then warmup {args.warmup}")
+    for s in range(preroll + args.warmup):
         step(s)
     torch.cuda.synchronize()
+    first = preroll + args.warmup
     events = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
-    log(f"[bench] timing {args.steps} steps")
+    log(f"[bench] timing {args.steps} steps (slices {first}..{first + args.steps - 1})")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
-        step(args.warmup + i, events[i])
+        step(first + i, events[i])
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ingest_ms = np.mean([e[0].elapsed_time(e[1]) for e in events])
@@ -304,25 +417,25 @@ def main() -> int:
     ms_per_step = elapsed * 1e3 / args.steps
 
     # update alone, and with the slice's host-to-device copy from pinned memory
-    pinned = torch.from_numpy(host_slices[0].view(np.int32)).pin_memory()
     staged = torch.empty_like(slices[0])
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
     h2d, upd = [], []
-    for _ in range(5):
+    for r in range(5):
+        pinned = torch.from_numpy(host_slices[(first + args.steps + r) % n_gen].view(np.int32)).pin_memory()
         ev[0].record()
         staged.copy_(pinned, non_blocking=True)
         ev[1].record()
-        sk.ingest(staged)
+        sk.ingest(staged)                   # the closed slice advances and preserves first
         ev[2].record()
+        sk.close_slice()
         torch.cuda.synchronize()
         h2d.append(ev[0].elapsed_time(ev[1]))
         upd.append(ev[1].elapsed_time(ev[2]))
-    sk.close_slice()
-    torch.cuda.synchronize()
     update = {"packets_per_s": wl.packets_per_slice / (float(np.median(upd)) * 1e-3),
               "packets_per_s_with_h2d": wl.packets_per_slice / ((float(np.median(upd)) +
                                                                   float(np.median(h2d))) * 1e-3),
-              "h2d_ms": float(np.median(h2d)), "note": "ingest call incl. advance + preservation"}
+              "h2d_ms": float(np.median(h2d)),
+              "note": "median of 5 ingest calls, each incl. the advance + preservation of the closed slice"}
 
     # the same slices with the host list planned once (the VAT addresses do
     # not depend on the pool): lookups, histograms and both estimates only
@@ -331,7 +444,7 @@ def main() -> int:
     pev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(args.steps)]
     t0 = time.perf_counter()
     for i in range(args.steps):
-        sk.ingest(slices[(args.warmup + i) % n_gen])
+        sk.ingest(slices[(first + args.steps + 5 + i) % n_gen])
         sk.close_slice()
         pev[i][0].record()
         L.estimate_learned_run(sk, weights, out=(est, est_cf))
@@ -375,7 +488,8 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": wl.name, "packets_per_slice": wl.packets_per_slice,
                    "hosts": pop.n_hosts, "log2_pool": wl.log2_pool, "width": wl.width,
-                   "k": wl.k, "kprime": wl.k, "g": wl.g, "slices_generated": n_gen},
+                   "k": wl.k, "kprime": wl.k, "g": wl.g, "slices_generated": n_gen,
+                   "slices_preroll": preroll, "slices_timed": [first, first + args.steps - 1]},
         "hosts_per_s": pop.n_hosts * args.steps / elapsed,
         "phases_ms": {"advance_preserve_ingest": ingest_ms, "census": census_ms,
                       "estimate": est_ms},
@@ -400,9 +514,8 @@ def main() -> int:
         del sk
         torch.cuda.empty_cache()
         line["batched"] = batched_leg(dev)
-    if not args.no_cpu_baseline:
-        log("[bench] cpu baseline (oracle)")
-        line["cpu_baseline"] = cpu_baseline(wl, pop, host_slices)
+    if cpu is not None:
+        line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
     return 0
 
