@@ -143,21 +143,22 @@ int vate_estimate(vate_sketch *s, const uint32_t *hosts_dev, size_t n_hosts,
                   uint32_t *hist_dev, void *stream);
 
 /* Device workspace (bytes) that vate_estimate_ws needs for n_hosts hosts:
- * about 6*g bytes per host (a 32-bit entry and a 16-bit result per VAT, runs
- * padded to 4) plus small tables.  Errors: VATE_E_INVAL. */
+ * about 8*g bytes per host (a 32-bit entry and a 32-bit slot for its live
+ * copy per VAT, runs padded to 4) plus the run table.  Errors: VATE_E_INVAL. */
 int vate_estimate_workspace_bytes(const vate_sketch *s, size_t n_hosts, size_t *bytes);
 
 /* Same results as vate_estimate (same outputs, layouts, errors; any k for the
  * histogram), computed with the VAT lookups (Alg. 4's estimate loop, Alg. 1)
  * reordered for locality: the hosts' VATs are hashed once and sorted into
- * the workspace by pool slice of 128 KiB of ATs, each slice's lookups are
- * resolved against that slice of the pool held in LDS, and every host's
- * distance histogram is rebuilt from the results.  workspace_dev (256-byte
+ * the workspace by pool slice of 2^20 ATs, each slice's lookups are tested
+ * against that slice's activity bits for window k (held in LDS), only the
+ * live VATs are kept and read from the pool for their distance, and every
+ * host's distance histogram is rebuilt from them.  workspace_dev (256-byte
  * aligned, at least vate_estimate_workspace_bytes) is scratch owned by the
  * caller; calls that share a workspace must not overlap.  Sketches outside
- * the path's limits (pools above 1 GiB, g above the sort's capacity, the
- * locality-blocked H) fall back to vate_estimate's gather.  Errors: as
- * vate_estimate, plus VATE_E_INVAL for a missing or small workspace. */
+ * the path's limits (g above the sort's capacity, the locality-blocked H)
+ * fall back to vate_estimate's gather.  Errors: as vate_estimate, plus
+ * VATE_E_INVAL for a missing or small workspace. */
 int vate_estimate_ws(vate_sketch *s, const uint32_t *hosts_dev, size_t n_hosts,
                      uint32_t kprime, float *est_dev, uint32_t *live_dev, uint32_t *hist_dev,
                      void *workspace_dev, size_t workspace_bytes, void *stream);
@@ -171,7 +172,7 @@ int vate_estimate_ws(vate_sketch *s, const uint32_t *hosts_dev, size_t n_hosts,
  * vate_estimate_ws.  Every call on one GPU shares that GPU's array, which
  * keeps the last call's contents: calls that overlap on one GPU (from any
  * sketch, stream or host thread) race and must not be issued.  The host
- * count is limited by the array: at g = 1024 about 10,000 hosts.
+ * count is limited by the array: at g = 1024 about 8,000 hosts.
  * Errors: as vate_estimate_ws; VATE_E_INVAL when the host count needs more
  * workspace than VATE_NOALLOC_SCRATCH_BYTES (vate_estimate_workspace_bytes
  * tells); VATE_E_DEVICE if the array's device address cannot be found. */

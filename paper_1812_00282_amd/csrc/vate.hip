@@ -887,37 +887,31 @@ static void launch_estimate_learned(vate_sketch *s, const uint32_t *hosts, uint3
 }
 
 // ---- partitioned estimate: geometry, workspace layout and launches ----
-// part_geo returns false when the sketch or host count is outside the
-// partitioned path's limits (a pool above 1 GiB, or g VATs of one host too
-// many for one LDS sort) or the sketch uses the locality-blocked H; the entry
-// points then use the direct gather.
+// part_geo returns false when the host count or g is outside the partitioned
+// path's limits (g VATs of one host too many for one LDS sort) or the sketch
+// uses the locality-blocked H; the entry points then use the direct gather.
 static bool part_geo(const vate_sketch *s, uint64_t n, PartGeo *out)
 {
     const Geo &G = s->G;
     if (G.blog > 0) return false;   // blocked VATs: the direct gather already reads whole blocks
-    const uint32_t w = s->p.width;
-    uint32_t wlog = 0;                                  // ceil(log2 w)
-    while ((1u << wlog) < w) ++wlog;
-    uint32_t sl = kSliceBytesLog2 + 3u - wlog;          // the most ATs of w bits in 128 KiB, a power of two
-    if (sl > G.c) sl = G.c;
+    const uint32_t sl = G.c < kSliceLog2 ? G.c : kSliceLog2;
     const uint64_t ns = G.N >> sl;
     if (ns > kRunMaxSlices) return false;
     PartGeo p{};
     p.sl = sl;
     p.n_slices = (uint32_t)ns;
-    p.sub = p.n_slices < kSuper ? p.n_slices : kSuper;
-    p.n_super = p.n_slices / p.sub;
-    p.xcd = p.n_super >= 8 ? 1u : 0u;
-    // Histogram rows of ceil((k+1)/2) words, made odd: most of a host's VATs
-    // land in its bin k, and an odd stride puts those bins of different hosts
-    // in different LDS banks (an even stride maps them onto few banks).
+    p.bm_words = sl >= 5 ? 1u << (sl - 5) : 1u;
+    p.xcd = ns >= 8 ? 1u : 0u;
+    // Histogram rows of ceil((k+1)/2) words, made odd: an odd stride puts
+    // the bins of different hosts in different LDS banks.
     p.rowp = ((G.k + 2u) / 2u) | 1u;
-    p.dbits = 1;                                        // distances 0..k and an all-ones padding mark
-    while ((1u << p.dbits) - 1u <= G.k) ++p.dbits;
+    p.dbits = 1;                                        // distances 0..k
+    while ((1u << p.dbits) - 1u < G.k) ++p.dbits;
     // Hosts per subgroup: the largest count whose VATs have 16-bit indices
     // (the scatter's sort slots and registers hold at most 65,535), whose
     // padded sort (+ slice counters, keys) fits its LDS, whose histograms fit
-    // the finalize's LDS, and whose host index fits a 16-bit result.
+    // the finalize's LDS, whose host index fits a 16-bit result and an entry
+    // beside the AT's offset within its slice.
     const uint64_t nsp = (ns + 3) & ~3ull;
     auto lds_for = [&](uint64_t hosts) {   // counters, keys, 16-bit sort slots
         const uint64_t cap = (hosts * G.g + 3 * ns + 3) & ~3ull;
@@ -939,14 +933,16 @@ static bool part_geo(const vate_sketch *s, uint64_t n, PartGeo *out)
     p.fast = G.a >= (1ull << sl) ? 1u : 0u;
     p.gmul = G.g == 1 ? 0u : (uint32_t)(((1ull << 32) + G.g - 1) / G.g);
     p.lds_scatter = (uint32_t)lds_for(hosts);
-    p.lds_lookup = (uint32_t)(((((uint64_t)w << sl) >> 3) + 15) & ~15ull);
-    p.lds_final = p.hosts * p.rowp * 4u;
-    // Each slice's walk over the subgroups is cut into kLookupSplit ranges
-    // (whole 1024-subgroup steps), one workgroup each: the eight workgroups of
-    // a super-slice then work on the same subgroups at about the same time,
-    // so the result lines they share meet in L2 more often.
-    p.split = std::max<uint32_t>(1u, std::min<uint32_t>(kLookupSplit, (p.n_sub + 1023u) / 1024u));
-    p.span = ((p.n_sub + p.split - 1u) / p.split + 1023u) & ~1023u;
+    p.lds_lookup = p.bm_words * 4u;
+    p.lds_final = p.hosts * p.rowp * 4u + 8u * (uint32_t)ns + 4u;
+    // Each slice's walk over the subgroups is cut into ranges, one workgroup
+    // each, so that the launch has about kLookupWgs workgroups; a range is a
+    // whole number of 64-subgroup windows (one per wavefront at a time) and
+    // holds at least one window per wavefront.
+    const uint32_t per_round = kRunThreads;   // 16 wavefronts x 64 subgroups
+    const uint32_t want = std::max<uint32_t>(1u, std::min<uint32_t>(kLookupWgs / p.n_slices, p.n_sub / per_round));
+    p.span = ((p.n_sub + want - 1u) / want + 63u) & ~63u;
+    p.split = (p.n_sub + p.span - 1u) / p.span;
     *out = p;
     return true;
 }
@@ -955,8 +951,8 @@ static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 struct RunWs {
     uint32_t *entries;          // [n_sub][region] sorted entries
-    uint16_t *res;              // [n_sub][region] lookup results: host within subgroup, distance
-    uint16_t *table;            // [n_super + 1][n_sub][sub] run starts
+    uint32_t *hits;             // [n_sub][region] live entries, packed at the front of each run's slots
+    uint32_t *table;            // [n_sub][n_slices + 1] run starts and live counts
     unsigned long long *cum;    // [k + 1] census prefix (several windows)
     size_t bytes;
 };
@@ -969,10 +965,10 @@ static RunWs run_ws(const PartGeo &pg, uint32_t k, void *base)
     size_t off = 0;
     w.entries = reinterpret_cast<uint32_t *>(p + off);
     off += align256(ents * 4);
-    w.res = reinterpret_cast<uint16_t *>(p + off);
-    off += align256(ents * 2);
-    w.table = reinterpret_cast<uint16_t *>(p + off);
-    off += align256((size_t)(pg.n_super + 1) * pg.n_sub * pg.sub * 2);
+    w.hits = reinterpret_cast<uint32_t *>(p + off);
+    off += align256(ents * 4);
+    w.table = reinterpret_cast<uint32_t *>(p + off);
+    off += align256((size_t)pg.n_sub * (pg.n_slices + 1) * 4);
     w.cum = reinterpret_cast<unsigned long long *>(p + off);
     off += align256((size_t)(k + 1) * 8);
     w.bytes = off;
@@ -1004,9 +1000,9 @@ static int launch_part(vate_sketch *s, const PartGeo &pg, void *ws, const uint32
     if (!(attr_set.load(std::memory_order_acquire) & bit)) {
         int rc = set_lds_limit(s, reinterpret_cast<const void *>(&k_run_scatter), s->lds_budget);
         if (rc == VATE_OK)
-            rc = set_lds_limit(s, reinterpret_cast<const void *>(&k_run_lookup<W>), 1u << kSliceBytesLog2);
+            rc = set_lds_limit(s, reinterpret_cast<const void *>(&k_run_lookup), 1u << (kSliceLog2 - 3));
         if (rc == VATE_OK)
-            rc = set_lds_limit(s, reinterpret_cast<const void *>(&k_run_finalize<MODE>), kFinHistBytes);
+            rc = set_lds_limit(s, reinterpret_cast<const void *>(&k_run_finalize<W, MODE>), kFinHistBytes + kFinRunBytes);
         if (rc != VATE_OK) return rc;
         attr_set.fetch_or(bit, std::memory_order_release);
     }
@@ -1015,11 +1011,11 @@ static int launch_part(vate_sketch *s, const PartGeo &pg, void *ws, const uint32
         k_run_scatter<<<std::min(pg.n_sub, s->n_cu), kRunThreads, pg.lds_scatter, st>>>(s->G, pg, hosts, n, w.entries,
                                                                                        w.table);
     if (steps == PART_PLAN) return VATE_OK;
-    k_run_lookup<W><<<pg.n_slices * pg.split, kRunThreads, pg.lds_lookup, st>>>(s->G, pg, s->pool, s->st, w.entries,
-                                                                                  w.table, w.res);
+    k_run_lookup<<<pg.n_slices * pg.split, kRunThreads, pg.lds_lookup, st>>>(
+        s->G, pg, reinterpret_cast<const uint32_t *>(s->bitmap), w.entries, w.table, w.hits);
     if (MODE == kFinMulti) k_census_prefix<<<1, 64, 0, st>>>(s->G, s->st, w.cum);
-    k_run_finalize<MODE><<<pg.n_sub, kFinThreads, pg.lds_final, st>>>(
-        s->G, pg, s->st, n, kprime, w.res, w.table, est, live, hist, win, w.cum,
+    k_run_finalize<W, MODE><<<pg.n_sub, kFinThreads, pg.lds_final, st>>>(
+        s->G, pg, s->pool, s->st, n, kprime, w.hits, w.table, est, live, hist, win, w.cum,
         static_cast<const mlp::Packed *>(weights), cf);
     return VATE_OK;
 }

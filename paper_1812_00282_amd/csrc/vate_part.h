@@ -4,37 +4,39 @@
 // namespace vate.
 //
 // The direct gather reads one random cache line per VAT anywhere in the
-// pool, so it is bound by line fills from beyond L2.  Here:
+// pool, so it is bound by line fills from beyond L2.  Here the pool is cut
+// into slices of 2^20 ATs, whose activity bits (the census bitmap: CheckAT
+// for the window k) fill 128 KiB of LDS:
 //
 //  k_run_scatter  persistent workgroups, one subgroup of hosts at a time.
 //                 Hashes the subgroup's VATs (their slices stay in
-//                 registers), counts them per pool slice in LDS, places their
+//                 registers), counts them per slice in LDS, places their
 //                 16-bit indices by an LDS counting sort (two bytes a slot is
 //                 what lets a subgroup hold 63 hosts of g = 1024), then
 //                 copies the sorted entries (host within subgroup, AT within
 //                 slice; the pid hashed again from the index) to the
 //                 workspace as one coalesced stream.  Every (subgroup, slice)
 //                 run starts on a 4-entry boundary (padded with kRunPad), so
-//                 no 16-byte chunk is shared by two slices.  Run starts, in
-//                 chunks, go to a u16 table laid out
-//                 [super-slice][subgroup][slice in super].
-//  k_run_lookup   one workgroup per pool slice (128 KiB of ATs, held in LDS).
-//                 Walks that slice's run in every subgroup and writes, beside
-//                 each entry, a 16-bit result: the host within the subgroup
-//                 and the VAT's distance (Eq. 5, CheckAT; k = inactive for
-//                 window k).  The 8 slices of a super-slice are given
-//                 to one XCD: their runs are adjacent in memory, so the lines
-//                 they read and the distance bytes they write meet in that
-//                 XCD's L2.  Each slice's walk is split over kLookupSplit
-//                 workgroups (ranges of subgroups).
-//  k_run_finalize one workgroup per subgroup.  Streams the results back,
-//                 builds each host's distance histogram in LDS and forms
-//                 Eq. 11 for k', several windows, or the learned estimate
-//                 (the network fed from the LDS histograms, 16 hosts per
-//                 wavefront).
+//                 no 16-byte chunk is shared by two runs.  Run starts, in
+//                 chunks, go to the subgroup's row of the run table.
+//  k_run_lookup   one slice's bits in LDS per workgroup (each slice's walk
+//                 over the subgroups split over a few workgroups on one XCD).
+//                 A wavefront takes the runs of eight subgroups as one flat
+//                 list of chunks, tests every entry's bit, and only for the
+//                 live ones (active for window k: a few per cent of the VATs
+//                 in steady state) reads the AT from the pool for its
+//                 distance (Eq. 5).  The live results - host within subgroup
+//                 and distance in 16 bits - are packed to the front of the
+//                 run's own result slots, ranked by ballot and popcount, and
+//                 the run's live count goes beside its start in the table.
+//  k_run_finalize one workgroup per subgroup.  Reads the live results of
+//                 its runs, builds each host's distance histogram in LDS (the
+//                 inactive bin k is g minus the rest) and forms Eq. 11 for
+//                 k', several windows, or the learned estimate (the network
+//                 fed from the LDS histograms, 16 hosts per wavefront).
 //
-// HBM traffic per VAT: 4 B entry written and read back once, 2 B result
-// written and read back once.
+// HBM traffic per VAT: the 4-byte entry written and read back once; per live
+// VAT a pool read and 2 bytes written and read back.
 
 constexpr uint32_t kRunThreads = 1024;                          // scatter / lookup workgroup
 constexpr uint32_t kRunPerThread = 64;                          // VATs hashed per scatter thread
@@ -42,23 +44,20 @@ constexpr uint32_t kRunMaxEntries = 65535;                      // VATs per subg
 constexpr uint32_t kSortPad = 0xFFFFu;                          // padding slot of the LDS sort
 constexpr uint32_t kRunLdsMax = 160u * 1024u;                   // gfx950 LDS per workgroup
 constexpr uint32_t kRunLdsStatic = 64u;                         // k_run_scatter's static LDS (wsum)
-constexpr uint32_t kSliceBytesLog2 = 17;                        // pool bytes per slice: 128 KiB
-constexpr uint32_t kRunMaxSlices = 8192;                        // pools up to 1 GiB
+constexpr uint32_t kSliceLog2 = 20;                             // ATs per slice: 2^20, 128 KiB of activity bits
+constexpr uint32_t kRunMaxSlices = 4096;                        // any pool up to 2^32 ATs
 constexpr uint32_t kRunMaxHosts = 1024;                         // hosts per subgroup
-constexpr uint32_t kRunPad = 0xFFFFFFFFu;                       // padding entry (never a real one: <= 28 bits)
-constexpr uint32_t kSuper = 8;                                  // slices per super-slice
+constexpr uint32_t kRunPad = 0xFFFFFFFFu;                       // padding entry (never a real one: host < 2^12)
 constexpr uint32_t kFinThreads = 256;
-constexpr uint32_t kLookupSplit = 2;                            // subgroup ranges per slice (lookup)
-constexpr uint32_t kLanesPerRun = 16;                           // lookup lanes per run, one 16-byte chunk each
-constexpr uint32_t kRunsPerStep = 64 / kLanesPerRun;            // runs per wavefront step
-constexpr uint32_t kSubPerWave = 8 * kRunsPerStep;              // subgroups per wavefront per pipeline stage
+constexpr uint32_t kLookU = 8;                                  // 16-byte entry chunks per lane and lookup pass
+constexpr uint32_t kLookupWgs = 2048;                           // lookup workgroups to aim for (8 per CU)
 constexpr uint32_t kFinHistBytes = 64u * 1024u;                 // per-subgroup histogram ceiling
+constexpr uint32_t kFinRunBytes = 8u * (kRunMaxSlices + 1u);    // run cells and chunk prefix in the finalize
 
 struct PartGeo {
     uint32_t sl;          // ATs per slice = 2^sl
     uint32_t n_slices;    // N >> sl
-    uint32_t sub;         // slices per super-slice, min(8, n_slices)
-    uint32_t n_super;     // n_slices / sub
+    uint32_t bm_words;    // 32-bit bitmap words per slice (at least one)
     uint32_t hosts;       // hosts per subgroup
     uint32_t n_sub;       // subgroups
     uint32_t vats;        // hosts * g
@@ -67,20 +66,25 @@ struct PartGeo {
     uint32_t dq, dr;      // kRunThreads = dq * g + dr
     uint32_t fast;        // every block holds >= 2^sl ATs: a slice meets at most two blocks
     uint32_t rowp;        // u32 words per packed 16-bit histogram row: ceil((k + 1) / 2), made odd
-    uint32_t xcd;         // map the slices of a super-slice to one XCD
+    uint32_t xcd;         // give the workgroups of one slice to one XCD
     uint32_t split;       // lookup workgroups per slice, each over a range of subgroups
-    uint32_t span;        // subgroups per range (a multiple of 1024)
+    uint32_t span;        // subgroups per range (a multiple of kGroupRuns)
     uint32_t lds_scatter, lds_lookup, lds_final;
-    uint32_t dbits;       // distance bits of a result: values 0..k, all ones = padding
+    uint32_t dbits;       // distance bits of a result: values 0..k
     uint32_t gmul;        // ceil(2^32 / g), v / g = umulhi(v, gmul) for v < 2^16; 0 for g = 1
 };
+
+// Run table: row s (n_slices + 1 cells of 32 bits) belongs to subgroup s.
+// Cell b < n_slices: the start of run (s, b) in 4-entry chunks (low half,
+// written by the scatter) and its live count (high half, written by the
+// lookup); cell n_slices: the subgroup's padded length in chunks.
 
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t pad4(uint32_t x) { return (x + 3u) & ~3u; }
 
 __global__ void __launch_bounds__(kRunThreads) k_run_scatter(Geo G, PartGeo PG, const uint32_t *__restrict__ hosts,
                                                             uint32_t n, uint32_t *__restrict__ entries,
-                                                            uint16_t *__restrict__ table)
+                                                            uint32_t *__restrict__ table)
 {
     extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
     __shared__ uint32_t wsum[kRunThreads / 64];
@@ -185,20 +189,11 @@ __global__ void __launch_bounds__(kRunThreads) k_run_scatter(Geo G, PartGeo PG, 
         uint32_t total = 0;
         for (uint32_t q = 0; q < kRunThreads / 64; ++q) total += wsum[q];
         __syncthreads();
-        // Run starts to the table in 4-entry chunks, one 16-byte
-        // (super-slice, subgroup) cell per store.
-        if (PG.sub == kSuper) {
-            for (uint32_t B = t; B < PG.n_super; B += kRunThreads) {
-                const uint32_t *c8 = cnt + 8u * B;
-                reinterpret_cast<uint4 *>(table)[(size_t)B * PG.n_sub + s] =
-                    make_uint4((c8[0] >> 2) | ((c8[1] >> 2) << 16), (c8[2] >> 2) | ((c8[3] >> 2) << 16),
-                               (c8[4] >> 2) | ((c8[5] >> 2) << 16), (c8[6] >> 2) | ((c8[7] >> 2) << 16));
-            }
-        } else {
-            for (uint32_t b = t; b < PG.n_slices; b += kRunThreads)
-                table[((size_t)(b / PG.sub) * PG.n_sub + s) * PG.sub + b % PG.sub] = (uint16_t)(cnt[b] >> 2);
-        }
-        if (t == 0) table[((size_t)PG.n_super * PG.n_sub + s) * PG.sub] = (uint16_t)(total >> 2);
+        // Run starts, in 4-entry chunks, to the subgroup's row of the table
+        // (live counts zero until the lookup writes them).
+        uint32_t *trow = table + (size_t)s * (PG.n_slices + 1);
+        for (uint32_t b = t; b < PG.n_slices; b += kRunThreads) trow[b] = cnt[b] >> 2;
+        if (t == 0) trow[PG.n_slices] = total >> 2;
         __syncthreads();
 
 #pragma unroll
@@ -235,156 +230,150 @@ __global__ void __launch_bounds__(kRunThreads) k_run_scatter(Geo G, PartGeo PG, 
 }
 
 // ---------------------------------------------------------------------------
-template <typename DT>
-__device__ __forceinline__ void store4(DT *p, const uint32_t d[4])
+// Component m of a 16-byte chunk, m in [0, 4).
+__device__ __forceinline__ uint32_t comp4(const uint4 &v, uint32_t m)
 {
-    if constexpr (sizeof(DT) == 1)
-        *reinterpret_cast<uint32_t *>(p) = d[0] | (d[1] << 8) | (d[2] << 16) | (d[3] << 24);
-    else
-        *reinterpret_cast<uint2 *>(p) = make_uint2(d[0] | (d[1] << 16), d[2] | (d[3] << 16));
+    return m == 0 ? v.x : m == 1 ? v.y : m == 2 ? v.z : v.w;
 }
 
-template <int W>
-__global__ void __launch_bounds__(kRunThreads) k_run_lookup(Geo G, PartGeo PG, const uint8_t *__restrict__ pool,
-                                                           const DevState *__restrict__ st,
+__global__ void __launch_bounds__(kRunThreads) k_run_lookup(Geo G, PartGeo PG, const uint32_t *__restrict__ bitmap,
                                                            const uint32_t *__restrict__ entries,
-                                                           const uint16_t *__restrict__ table,
-                                                           uint16_t *__restrict__ res)
+                                                           uint32_t *__restrict__ table, uint32_t *__restrict__ hits_out)
 {
-    extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
-    const uint8_t *at = reinterpret_cast<const uint8_t *>(lds);
-    uint32_t B, j;
-    uint32_t part;                                  // subgroup range of this workgroup
-    if (PG.xcd) {              // workgroup x runs on XCD x mod 8
-        const uint32_t r = blockIdx.x & 7u, rest = blockIdx.x >> 3;
-        j = rest % PG.sub;
-        const uint32_t rest2 = rest / PG.sub;
-        part = rest2 % PG.split;
-        B = (rest2 / PG.split) * 8u + r;
+    extern __shared__ __attribute__((aligned(16))) uint32_t bm[];   // the slice's activity bits
+    uint32_t b, part;
+    if (PG.xcd) {              // workgroup x runs on XCD x mod 8: a slice's workgroups share one L2
+        const uint32_t r = blockIdx.x & 7u, u = blockIdx.x >> 3;
+        part = u % PG.split;
+        b = ((u / PG.split) << 3) | r;
     } else {
-        j = blockIdx.x % PG.sub;
-        const uint32_t rest2 = blockIdx.x / PG.sub;
-        part = rest2 % PG.split;
-        B = rest2 / PG.split;
+        part = blockIdx.x % PG.split;
+        b = blockIdx.x / PG.split;
     }
     const uint32_t s_lo = part * PG.span, s_hi = min(PG.n_sub, s_lo + PG.span);
-    const uint32_t b = B * PG.sub + j;
-    const uint32_t sl = PG.sl, mask = (1u << sl) - 1u;
-    const uint32_t nbytes = (uint32_t)(((uint64_t)(W ? W : G.wb) << sl) >> 3);
-    const uint8_t *src = pool + (uint64_t)b * nbytes;
-    if ((nbytes & 15u) == 0) {
-        for (uint32_t q = threadIdx.x; q < nbytes / 16; q += kRunThreads)
-            reinterpret_cast<uint4 *>(lds)[q] = reinterpret_cast<const uint4 *>(src)[q];
-    } else {
-        for (uint32_t q = threadIdx.x; q < nbytes; q += kRunThreads)
-            reinterpret_cast<uint8_t *>(lds)[q] = src[q];
+    const uint32_t mask = (1u << PG.sl) - 1u;
+    {
+        const uint32_t nw = PG.bm_words;
+        const uint32_t *src = bitmap + (size_t)b * nw;
+        if ((nw & 3u) == 0) {
+            for (uint32_t q = threadIdx.x; q < nw / 4; q += kRunThreads)
+                reinterpret_cast<uint4 *>(bm)[q] = reinterpret_cast<const uint4 *>(src)[q];
+        } else {
+            for (uint32_t q = threadIdx.x; q < nw; q += kRunThreads) bm[q] = src[q];
+        }
     }
     __syncthreads();
 
-    const uint32_t bact0 = st->bact0;
-    const uint32_t inact = inactive_value(G);
-    const uint32_t first = b << sl;
-    uint32_t act0 = 0, act1 = 0, split = 0;
-    if (PG.fast) {             // the slice meets block bid0 and at most block bid0 + 1
-        const uint32_t bid0 = block_of(G, first);
-        act0 = block_act(G, bact0, bid0);
-        const uint64_t nxt = block_start(G, bid0 + 1);
-        split = nxt - first > (uint64_t)mask ? mask + 1u : (uint32_t)(nxt - first);
-        act1 = block_act(G, bact0, bid0 + 1 < G.twok ? bid0 + 1 : bid0);
-    }
-    auto dist_of = [&](uint32_t local) -> uint32_t {
-        const uint32_t v = load_at<W>(at, local, G.wb);
-        if (v == inact) return G.k;
-        uint32_t d;
-        if (G.dr) {
-            d = v;
-        } else {
-            const uint32_t act = PG.fast ? (local < split ? act0 : act1)
-                                         : block_act(G, bact0, block_of(G, first | local));
-            d = at_dist(G, act, v);
-        }
-        return d < G.k ? d : G.k;
-    };
-
-    // kLanesPerRun lanes per subgroup run, four entries (one 16-byte chunk)
-    // per lane.  A wavefront takes kSubPerWave subgroups at a time: one
-    // coalesced read of their run bounds, then the first chunk of eight runs
-    // per lane group is loaded before any is used (eight independent loads in
-    // flight per lane); the rare chunks beyond a run's first kLanesPerRun
-    // follow in a second pass.
     const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
-    const uint32_t grp = lane / kLanesPerRun, gl = lane % kLanesPerRun;
-    const size_t row = (size_t)B * PG.n_sub, next_row = (size_t)(B + 1) * PG.n_sub;
-    // Runs start and end on 4-entry boundaries: every chunk belongs to one
-    // run.  A padding entry's result is all ones.
-    auto resolve = [&](uint32_t s, uint32_t c, const uint4 &e4) {
-        const uint32_t e[4] = {e4.x, e4.y, e4.z, e4.w};
-        uint32_t r[4];
-#pragma unroll
-        for (int m = 0; m < 4; ++m)
-            r[m] = e[m] == kRunPad ? 0xFFFFu : (((e[m] >> sl) << PG.dbits) | dist_of(e[m] & mask));
-        store4<uint16_t>(res + (size_t)s * PG.region + 4u * c, r);
-    };
-    // Software pipeline over groups of 64 subgroups: while group i is
-    // resolved, the entries of group i + 1 and the run bounds of group i + 2
-    // are already in flight.
-    auto bounds = [&](uint32_t s0, uint32_t &st_l, uint32_t &en_l) {
-        st_l = en_l = 0;
-        if (lane < kSubPerWave && s0 + lane < s_hi) {
-            const size_t cell = (row + s0 + lane) * PG.sub;
-            st_l = table[cell + j];
-            en_l = j + 1 < PG.sub ? table[cell + j + 1] : table[(next_row + s0 + lane) * PG.sub];
+    const uint64_t lt = (1ull << lane) - 1ull;
+    const uint32_t row = PG.n_slices + 1;
+    uint16_t *tab16 = reinterpret_cast<uint16_t *>(table);
+    const uint4 *ent4 = reinterpret_cast<const uint4 *>(entries);
+    const uint32_t rq = PG.region / 4;
+    constexpr uint32_t kPass = 64u * kLookU;
+    // A wavefront takes windows of 64 subgroups (lane r: run r of the
+    // window), kRunThreads subgroups apart.  The window's runs in this slice
+    // are one flat list of chunks (run after run), read in passes of kLookU
+    // chunks per lane.  A live entry's rank in the flat list minus the rank
+    // of its run's first chunk is its slot among the run's live results.
+    for (uint32_t s0 = s_lo + wv * 64u; s0 < s_hi; s0 += kRunThreads) {
+        uint32_t Sv = 0, len = 0;      // lane r: start (chunks) and length of run r
+        if (s0 + lane < s_hi) {
+            const size_t cell = (size_t)(s0 + lane) * row + b;
+            Sv = tab16[2 * cell];
+            len = (uint32_t)tab16[2 * cell + 2] - Sv;
         }
-    };
-    auto issue = [&](uint32_t s0, uint32_t st_l, uint32_t en_l, uint4 e4[8]) {
+        uint32_t incl = len;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const uint32_t r = kRunsPerStep * q + grp;
-            const uint32_t start = __shfl(st_l, (int)r, 64), end = __shfl(en_l, (int)r, 64);
-            const uint32_t c = start + gl;
-            e4[q] = make_uint4(0u, 0u, 0u, 0u);
-            if (c < end) e4[q] = reinterpret_cast<const uint4 *>(entries + (size_t)(s0 + r) * PG.region)[c];
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(incl, off, 64);
+            if (lane >= (uint32_t)off) incl += y;
         }
-    };
-    auto finish = [&](uint32_t s0, uint32_t st_l, uint32_t en_l, const uint4 e4[8]) {
+        const uint32_t Fv = incl - len;                         // run r's first chunk in the flat list
+        const uint32_t Ftot = __builtin_amdgcn_readlane(incl, 63);
+        uint32_t Pv = 0;                                        // live entries before run r's first chunk
+        uint32_t hits = 0;                                      // live entries of the window so far
+        for (uint32_t base = 0; base < Ftot; base += kPass) {
+            uint4 e4[kLookU];
+            uint32_t jr[kLookU];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const uint32_t r = kRunsPerStep * q + grp;
-            const uint32_t start = __shfl(st_l, (int)r, 64), end = __shfl(en_l, (int)r, 64);
-            const uint32_t c = start + gl;
-            if (c < end) resolve(s0 + r, c, e4[q]);
-        }
-        // Chunks beyond a run's first kLanesPerRun, when any run of the
-        // group has them (rare: runs average about a third of that).
-        if (!__ballot(en_l - st_l > kLanesPerRun)) return;
-        for (int q = 0; q < 8; ++q) {
-            const uint32_t r = kRunsPerStep * q + grp;
-            const uint32_t start = __shfl(st_l, (int)r, 64), end = __shfl(en_l, (int)r, 64);
-            const uint32_t s = s0 + r, c1 = end;
-            const uint4 *ent = reinterpret_cast<const uint4 *>(entries + (size_t)s * PG.region);
-            for (uint32_t c = start + kLanesPerRun + gl;; c += kLanesPerRun) {
-                const bool act = c < c1;
-                if (!__ballot(act)) break;
-                if (act) resolve(s, c, ent[c]);
+            for (uint32_t q = 0; q < kLookU; ++q) {
+                const uint32_t i0 = base + 64u * q, i = i0 + lane;
+                e4[q] = make_uint4(kRunPad, kRunPad, kRunPad, kRunPad);
+                jr[q] = 0;
+                if (i0 < Ftot) {
+                    // run of chunk i: the last r with F_r <= i (F is nondecreasing,
+                    // and an empty run shares its F with the next)
+                    const uint32_t last = min(i0 + 63u, Ftot - 1u);
+                    const uint32_t jb = (uint32_t)__popcll(__ballot(Fv <= i0)) - 1u;
+                    const uint32_t je = (uint32_t)__popcll(__ballot(Fv <= last)) - 1u;
+                    uint32_t j = jb;
+                    uint32_t Fj = __builtin_amdgcn_readlane(Fv, jb), Sj = __builtin_amdgcn_readlane(Sv, jb);
+                    for (uint32_t jj = jb + 1; jj <= je; ++jj) {
+                        const uint32_t f = __builtin_amdgcn_readlane(Fv, jj);
+                        const uint32_t sj = __builtin_amdgcn_readlane(Sv, jj);
+                        if (i >= f) j = jj, Fj = f, Sj = sj;
+                    }
+                    jr[q] = j;
+                    if (i < Ftot) e4[q] = ent4[(size_t)(s0 + j) * rq + Sj + (i - Fj)];
+                }
+            }
+            // live bits (CheckAT for window k) of the lane's entries
+            uint64_t M = 0;
+#pragma unroll
+            for (uint32_t q = 0; q < kLookU; ++q)
+#pragma unroll
+                for (uint32_t m = 0; m < 4; ++m) {
+                    const uint32_t e = comp4(e4[q], m);
+                    const uint32_t o = e & mask;
+                    const uint32_t hit = e != kRunPad ? (bm[o >> 5] >> (o & 31u)) & 1u : 0u;
+                    M |= (uint64_t)hit << (4u * q + m);
+                }
+            // rank of the lane's first live entry per chunk in the flat list
+            uint32_t hb[kLookU];
+#pragma unroll
+            for (uint32_t q = 0; q < kLookU; ++q) {
+                const uint32_t nib = (uint32_t)(M >> (4u * q)) & 0xFu;
+                uint32_t below = 0, tot = 0;
+#pragma unroll
+                for (uint32_t m = 0; m < 4; ++m) {
+                    const uint64_t bal = __ballot((nib >> m) & 1u);
+                    below += (uint32_t)__popcll(bal & lt);
+                    tot += (uint32_t)__popcll(bal);
+                }
+                hb[q] = hits + below;
+                hits += tot;
+            }
+            // runs whose first chunk is in this pass: live entries before it
+            {
+                const uint32_t off = Fv - base, qj = off >> 6, lj = off & 63u;
+                uint32_t v = 0;
+#pragma unroll
+                for (uint32_t q = 0; q < kLookU; ++q) {
+                    const uint32_t t = __shfl(hb[q], (int)lj, 64);
+                    if (q == qj) v = t;
+                }
+                if (Fv >= base && Fv < base + kPass && Fv < Ftot) Pv = v;
+            }
+            // live entries to the front of their run's result slots
+#pragma unroll
+            for (uint32_t q = 0; q < kLookU; ++q) {
+                const uint32_t nib = (uint32_t)(M >> (4u * q)) & 0xFu;
+                const uint32_t Sj = __shfl(Sv, (int)jr[q], 64), Pj = __shfl(Pv, (int)jr[q], 64);
+                if (nib) {
+                    uint32_t *dst = hits_out + (size_t)(s0 + jr[q]) * PG.region + 4u * Sj + (hb[q] - Pj);
+#pragma unroll
+                    for (uint32_t m = 0; m < 4; ++m)
+                        if ((nib >> m) & 1u) *dst++ = comp4(e4[q], m);
+                }
             }
         }
-    };
-    const uint32_t step = (kRunThreads / 64) * kSubPerWave;   // 16 wavefronts
-    uint32_t s0 = s_lo + wv * kSubPerWave;
-    uint32_t stA, enA, stB, enB;
-    uint4 eA[8];
-    bounds(s0, stA, enA);
-    issue(s0, stA, enA, eA);
-    bounds(s0 + step, stB, enB);
-    for (; s0 < s_hi; s0 += step) {
-        uint4 eB[8];
-        issue(s0 + step, stB, enB, eB);
-        uint32_t stC, enC;
-        bounds(s0 + 2 * step, stC, enC);
-        finish(s0, stA, enA, eA);
-#pragma unroll
-        for (int q = 0; q < 8; ++q) eA[q] = eB[q];
-        stA = stB, enA = enB, stB = stC, enB = enC;
+        // live count of each run beside its start (the shuffle with every
+        // lane active: a lane reads its neighbour's value)
+        const uint32_t pf = Fv < Ftot ? Pv : hits;
+        const uint32_t pn = __shfl_down(pf, 1, 64);
+        if (s0 + lane < s_hi)
+            tab16[2 * ((size_t)(s0 + lane) * row + b) + 1] = (uint16_t)((lane == 63 ? hits : pn) - pf);
     }
 }
 
@@ -449,53 +438,107 @@ __device__ __forceinline__ void learned16(const Geo &G, float occupancy, const u
 // At least 5 wavefronts per SIMD: the network's registers would otherwise
 // hold the streaming pass to 4 (measured 0.64 against 0.58 ms on the 40G
 // workload; 6 would spill).
-template <int MODE>
-__global__ void __launch_bounds__(kFinThreads, 5) k_run_finalize(Geo G, PartGeo PG, const DevState *__restrict__ st,
+template <int W, int MODE>
+__global__ void __launch_bounds__(kFinThreads, 5) k_run_finalize(Geo G, PartGeo PG, const uint8_t *__restrict__ pool,
+                                                             const DevState *__restrict__ st,
                                                              uint32_t n, uint32_t kprime,
-                                                             const uint16_t *__restrict__ res,
-                                                             const uint16_t *__restrict__ table, float *__restrict__ est,
+                                                             const uint32_t *__restrict__ hits,
+                                                             const uint32_t *__restrict__ table, float *__restrict__ est,
                                                              uint32_t *__restrict__ live_out,
                                                              uint32_t *__restrict__ hist_out, Windows win,
                                                              const unsigned long long *__restrict__ cum,
                                                              const mlp::Packed *__restrict__ P,
                                                              float *__restrict__ cf_out)
 {
-    extern __shared__ __attribute__((aligned(16))) uint32_t hist[];   // [hosts][rowp] packed 16-bit bins
+    // [hosts][rowp] packed 16-bit bins, then the subgroup's run cells and the
+    // prefix of their live entries in 4-entry pieces
+    extern __shared__ __attribute__((aligned(16))) uint32_t hist[];
+    __shared__ uint32_t wtot[kFinThreads / 64];
     const uint32_t s = blockIdx.x, t = threadIdx.x;
     const uint32_t h0 = s * PG.hosts;
     const uint32_t nh = min(PG.hosts, n - h0);
-    const uint32_t nvp = 4u * table[((size_t)PG.n_super * PG.n_sub + s) * PG.sub];   // padded entries
     const uint32_t rowp = PG.rowp;
+    const uint32_t ns = PG.n_slices;
+    uint32_t *cell = hist + nh * rowp;          // [ns] run cells
+    uint32_t *pre = cell + ns;                  // [ns + 1] pieces before run b
     for (uint32_t q = t; q < nh * rowp; q += kFinThreads) hist[q] = 0;
+    // Exclusive prefix of the runs' piece counts: thread t owns runs
+    // [t rs, (t+1) rs).
+    const uint32_t *trow = table + (size_t)s * (ns + 1);
+    const uint32_t rs = (ns + kFinThreads - 1) / kFinThreads;
+    // (a live count never exceeds the run's slots; the clamp keeps every read
+    // inside them whatever the table holds)
+    auto pieces = [&](uint32_t b, uint32_t c) {
+        const uint32_t len = (trow[b + 1] & 0xFFFFu) - (c & 0xFFFFu);
+        return min(((c >> 16) + 3u) >> 2, len);
+    };
+    uint32_t mine = 0;
+    for (uint32_t q = 0; q < rs; ++q) {
+        const uint32_t b = t * rs + q;
+        if (b < ns) {
+            const uint32_t c = trow[b];
+            const uint32_t np = pieces(b, c);
+            cell[b] = (c & 0xFFFFu) | (min(c >> 16, 4u * np) << 16);
+            mine += np;
+        }
+    }
+    const uint32_t lane = t & 63u, wv = t >> 6;
+    uint32_t incl = mine;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(incl, off, 64);
+        if (lane >= (uint32_t)off) incl += y;
+    }
+    if (lane == 63) wtot[wv] = incl;
+    __syncthreads();
+    uint32_t run = incl - mine, total = 0;
+    for (uint32_t q = 0; q < kFinThreads / 64; ++q) {
+        if (q < wv) run += wtot[q];
+        total += wtot[q];
+    }
+    for (uint32_t q = 0; q < rs; ++q) {
+        const uint32_t b = t * rs + q;
+        if (b < ns) {
+            pre[b] = run;
+            run += ((cell[b] >> 16) + 3u) >> 2;    // the clamped count's pieces
+        }
+    }
+    if (t == 0) pre[ns] = total;
     __syncthreads();
     {
-        const uint4 *rr = reinterpret_cast<const uint4 *>(res + (size_t)s * PG.region);   // 8 results per load
-        const uint32_t dmask = (1u << PG.dbits) - 1u;
-        constexpr uint32_t U = 8;     // loads in flight per thread
-        const uint32_t nch = (nvp + 7u) >> 3;     // nvp is a multiple of 4
-        for (uint32_t c0 = t; c0 < nch; c0 += U * kFinThreads) {
-            uint4 r4[U];
+        // Live entries: piece c (up to 4 entries, 16 bytes) belongs to the run
+        // b with pre[b] <= c < pre[b + 1].  Each entry's AT is read from the
+        // pool for its distance (Eq. 5) and counted into its host's bin with
+        // an LDS atomic.  Bin k (inactive) is not counted: it is g minus the
+        // others, filled in below.
+        const uint4 *hh = reinterpret_cast<const uint4 *>(hits + (size_t)s * PG.region);
+        const uint32_t sl = PG.sl, mask = (1u << sl) - 1u;
+        const uint32_t bact0 = st->bact0;
+        const uint32_t inact = inactive_value(G);
+        for (uint32_t c = t; c < total; c += kFinThreads) {
+            uint32_t lo = 0, hi = ns;                // largest b with pre[b] <= c
+            while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (pre[mid] <= c) lo = mid; else hi = mid;
+            }
+            const uint32_t k4 = c - pre[lo];
+            const uint32_t cb = cell[lo];
+            const uint32_t nr = min(4u, (cb >> 16) - 4u * k4);
+            const uint4 w4 = hh[(cb & 0xFFFFu) + k4];
+            const uint32_t first = lo << sl;
+            uint32_t e[4], v[4];
 #pragma unroll
-            for (uint32_t u = 0; u < U; ++u) {
-                const uint32_t c = c0 + u * kFinThreads;
-                if (c < nch) r4[u] = rr[c];
+            for (uint32_t m = 0; m < 4; ++m) {
+                e[m] = comp4(w4, m);
+                v[m] = m < nr ? load_at<W>(pool, first | (e[m] & mask), G.wb) : inact;
             }
 #pragma unroll
-            for (uint32_t u = 0; u < U; ++u) {
-                const uint32_t c = c0 + u * kFinThreads;
-                if (c >= nch) break;
-                const uint32_t w[4] = {r4[u].x, r4[u].y, r4[u].z, r4[u].w};
-#pragma unroll
-                for (int m = 0; m < 8; ++m) {
-                    if (8u * c + m >= nvp) break;
-                    // Bin k (inactive for window k, most of the VATs) and
-                    // padding (d all ones) are not counted: bin k is g minus
-                    // the others, filled in below.
-                    const uint32_t r = (w[m >> 1] >> ((m & 1) << 4)) & 0xFFFFu;
-                    const uint32_t d = r & dmask;
-                    if (d >= G.k) continue;
-                    atomicAdd(&hist[(r >> PG.dbits) * rowp + (d >> 1)], 1u << ((d & 1u) << 4));
-                }
+            for (uint32_t m = 0; m < 4; ++m) {
+                if (v[m] == inact) continue;
+                const uint32_t pid = first | (e[m] & mask);
+                const uint32_t d = value_dist(G, bact0, pid, v[m]);
+                if (d >= G.k) continue;
+                atomicAdd(&hist[(e[m] >> sl) * rowp + (d >> 1)], 1u << ((d & 1u) << 4));
             }
         }
     }

@@ -396,21 +396,24 @@ def test_multi_window_estimates(w, k, c):
 
 
 @pytest.mark.parametrize("c,w,k,g,partition,n_hosts", [
-    (20, 8, 60, 1024, 0, 1000),     # 8 slices: one super-slice
-    (22, 4, 7, 100, 1, 777),        # g not a power of two, ragged last subgroup
+    (20, 8, 60, 1024, 0, 1000),     # the pool is one slice of 2^20 ATs
+    (22, 4, 7, 100, 1, 777),        # g not a power of two, ragged last subgroup, 4 slices
     (21, 16, 300, 512, 0, 500),     # k >= 255: 16-bit distances
-    (23, 8, 30, 2048, 0, 300),      # 64 slices (XCD mapping), g above the workgroup size
+    (23, 8, 30, 2048, 0, 300),      # 8 slices (XCD mapping), g above the workgroup size
     (20, 8, 100, 64, 1, 3000),      # blocks shorter than a slice (per-AT block lookup)
-    (18, 8, 5, 1, 0, 5000),         # g = 1: 1024 hosts per subgroup
+    (18, 8, 5, 1, 0, 5000),         # g = 1: 1024 hosts per subgroup, a pool smaller than a slice
     (18, 8, 5, 3, 0, 2500),         # g = 3
-    (23, 7, 60, 1024, 0, 300),      # exact 7-bit ATs, 64 slices of 2^17
-    (21, 10, 300, 512, 1, 500),     # exact 10-bit ATs (slices of 2^16), 16-bit distances
+    (23, 7, 60, 1024, 0, 300),      # exact 7-bit ATs
+    (21, 10, 300, 512, 1, 500),     # exact 10-bit ATs, 16-bit distances
     (20, 8, 12, 100, 0, 200_000),   # 655 hosts per subgroup, 306 subgroups: persistent scatter
-                                    # workgroups take two each, ragged last one, v / g by multiply-high
-    (24, 8, 60, 1024, 0, 20_000),   # 63 hosts per subgroup (the 16-bit sort's limit), 318 subgroups
+                                    # workgroups, ragged last one, v / g by multiply-high
+    (24, 8, 60, 1024, 0, 20_000),   # 63 hosts per subgroup (the 16-bit sort's limit), 318
+                                    # subgroups, each slice's walk split over two workgroups
     (22, 4, 7, 100, 1, 200_000),    # 4-bit ATs, low-deviation partition, 306 subgroups
     (21, 16, 129, 64, 0, 100_000),  # 16-bit ATs, 252 hosts per subgroup, 397 subgroups
     (23, 10, 300, 256, 0, 50_000),  # exact 10-bit ATs, 108 hosts per subgroup, 463 subgroups
+    (26, 8, 40, 1024, 0, 40_000),   # 64 slices, 635 subgroups: slice walks split in four (XCD mapping)
+    (12, 8, 9, 64, 0, 4000),        # a pool of 4096 ATs (one slice of 128 activity words), dense hits
 ])
 def test_partitioned_geometries(c, w, k, g, partition, n_hosts):
     """The partitioned lookups across their geometry cases: live counts,
