@@ -194,21 +194,14 @@ def cpu_baseline(wl, pop, slices, sample_hosts: int = 4096, measured: int = 4,
     }
 
 
-def _gen_slice(args):
-    wl, pop, s = args
-    return wl.slice(pop, s)
-
-
 def generate_slices(wl, pop, n: int) -> list:
-    """The workload's first n slices (numpy, seeded per slice), drawn by
-    forked worker processes (before the GPU is touched)."""
-    import multiprocessing as mp
+    """The workload's first n slices (numpy, seeded per slice), drawn by a
+    pool of threads (no fork: under a profiler the GPU is already open)."""
+    from concurrent.futures import ThreadPoolExecutor
 
     workers = max(1, min(16, cpu_info()["nproc"], n))
-    if workers == 1:
-        return [wl.slice(pop, s) for s in range(n)]
-    with mp.get_context("fork").Pool(workers) as pool:
-        return pool.map(_gen_slice, [(wl, pop, s) for s in range(n)])
+    with ThreadPoolExecutor(workers) as ex:
+        return list(ex.map(lambda s: wl.slice(pop, s), range(n)))
 
 
 def batched_leg(dev, n_slices: int = 8) -> dict:
@@ -401,6 +394,9 @@ def main() -> int:
     log(f"[bench] pre-roll {preroll} slices, then warmup {args.warmup}")
     for s in range(preroll + args.warmup):
         step(s)
+        if (s + 1) % 20 == 0:
+            torch.cuda.synchronize()
+            log(f"[bench] slice {s + 1} of {preroll + args.warmup} untimed")
     torch.cuda.synchronize()
     first = preroll + args.warmup
     events = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]

@@ -905,22 +905,18 @@ static bool part_geo(const vate_sketch *s, uint64_t n, PartGeo *out)
     // Histogram rows of ceil((k+1)/2) words, made odd: an odd stride puts
     // the bins of different hosts in different LDS banks.
     p.rowp = ((G.k + 2u) / 2u) | 1u;
-    p.dbits = 1;                                        // distances 0..k
-    while ((1u << p.dbits) - 1u < G.k) ++p.dbits;
-    // Hosts per subgroup: the largest count whose VATs have 16-bit indices
-    // (the scatter's sort slots and registers hold at most 65,535), whose
-    // padded sort (+ slice counters, keys) fits its LDS, whose histograms fit
-    // the finalize's LDS, whose host index fits a 16-bit result and an entry
-    // beside the AT's offset within its slice.
+    // Hosts per subgroup: the largest count whose VATs' pids fit the scatter
+    // threads' registers (kRunPerThread each), whose padded sort of 32-bit
+    // entries (+ slice counters, keys) fits its LDS, and whose histograms fit
+    // the finalize's LDS.
     const uint64_t nsp = (ns + 3) & ~3ull;
-    auto lds_for = [&](uint64_t hosts) {   // counters, keys, 16-bit sort slots
+    auto lds_for = [&](uint64_t hosts) {   // counters, keys, 32-bit sort slots
         const uint64_t cap = (hosts * G.g + 3 * ns + 3) & ~3ull;
-        return 4 * (nsp + ((hosts + 3) & ~3ull)) + 2 * cap;
+        return 4 * (nsp + ((hosts + 3) & ~3ull)) + 4 * cap;
     };
     uint64_t hosts = kRunMaxHosts;
-    hosts = std::min<uint64_t>(hosts, kRunMaxEntries / G.g);
+    hosts = std::min<uint64_t>(hosts, (uint64_t)kRunPerThread * kRunThreads / G.g);
     hosts = std::min<uint64_t>(hosts, kFinHistBytes / (4ull * p.rowp));
-    hosts = std::min<uint64_t>(hosts, 1ull << (16 - p.dbits));   // host and distance share a 16-bit result
     while (hosts > 0 && lds_for(hosts) > s->lds_budget) --hosts;
     if (hosts == 0) return false;
     p.hosts = (uint32_t)hosts;
@@ -931,10 +927,23 @@ static bool part_geo(const vate_sketch *s, uint64_t n, PartGeo *out)
     p.dq = kRunThreads / G.g;
     p.dr = kRunThreads % G.g;
     p.fast = G.a >= (1ull << sl) ? 1u : 0u;
-    p.gmul = G.g == 1 ? 0u : (uint32_t)(((1ull << 32) + G.g - 1) / G.g);
+    // Subgroups per finalize workgroup: the network takes hosts in tiles of
+    // 64, so the count whose hosts leave the least of their last tile empty
+    // (the fewest on a tie), as long as the histograms and run cells fit.
+    {
+        uint32_t best = 1;
+        double waste = 1e30;
+        for (uint32_t f = 1; f <= 16; ++f) {
+            const uint64_t fh = f * hosts;
+            if (fh * 4ull * p.rowp > kFinHistBytes || (uint64_t)f * ns > kRunMaxSlices) break;
+            const double w = (double)(((fh + 63) / 64) * 64 - fh) / (double)fh;
+            if (w < waste - 1e-9) waste = w, best = f;
+        }
+        p.fgroup = best;
+    }
     p.lds_scatter = (uint32_t)lds_for(hosts);
     p.lds_lookup = p.bm_words * 4u;
-    p.lds_final = p.hosts * p.rowp * 4u + 8u * (uint32_t)ns + 4u;
+    p.lds_final = p.fgroup * p.hosts * p.rowp * 4u + 8u * p.fgroup * (uint32_t)ns + 4u;
     // Each slice's walk over the subgroups is cut into ranges, one workgroup
     // each, so that the launch has about kLookupWgs workgroups; a range is a
     // whole number of 64-subgroup windows (one per wavefront at a time) and
@@ -1014,7 +1023,7 @@ static int launch_part(vate_sketch *s, const PartGeo &pg, void *ws, const uint32
     k_run_lookup<<<pg.n_slices * pg.split, kRunThreads, pg.lds_lookup, st>>>(
         s->G, pg, reinterpret_cast<const uint32_t *>(s->bitmap), w.entries, w.table, w.hits);
     if (MODE == kFinMulti) k_census_prefix<<<1, 64, 0, st>>>(s->G, s->st, w.cum);
-    k_run_finalize<W, MODE><<<pg.n_sub, kFinThreads, pg.lds_final, st>>>(
+    k_run_finalize<W, MODE><<<(pg.n_sub + pg.fgroup - 1) / pg.fgroup, kFinThreads, pg.lds_final, st>>>(
         s->G, pg, s->pool, s->st, n, kprime, w.hits, w.table, est, live, hist, win, w.cum,
         static_cast<const mlp::Packed *>(weights), cf);
     return VATE_OK;

@@ -39,9 +39,7 @@
 // VAT a pool read and 2 bytes written and read back.
 
 constexpr uint32_t kRunThreads = 1024;                          // scatter / lookup workgroup
-constexpr uint32_t kRunPerThread = 64;                          // VATs hashed per scatter thread
-constexpr uint32_t kRunMaxEntries = 65535;                      // VATs per subgroup: 16-bit indices, one value spare
-constexpr uint32_t kSortPad = 0xFFFFu;                          // padding slot of the LDS sort
+constexpr uint32_t kRunPerThread = 40;                          // VATs hashed per scatter thread (pids held in registers)
 constexpr uint32_t kRunLdsMax = 160u * 1024u;                   // gfx950 LDS per workgroup
 constexpr uint32_t kRunLdsStatic = 64u;                         // k_run_scatter's static LDS (wsum)
 constexpr uint32_t kSliceLog2 = 20;                             // ATs per slice: 2^20, 128 KiB of activity bits
@@ -49,6 +47,7 @@ constexpr uint32_t kRunMaxSlices = 4096;                        // any pool up t
 constexpr uint32_t kRunMaxHosts = 1024;                         // hosts per subgroup
 constexpr uint32_t kRunPad = 0xFFFFFFFFu;                       // padding entry (never a real one: host < 2^12)
 constexpr uint32_t kFinThreads = 256;
+constexpr uint32_t kFinPieces = 4;                              // live-entry pieces a finalize thread has in flight
 constexpr uint32_t kLookU = 8;                                  // 16-byte entry chunks per lane and lookup pass
 constexpr uint32_t kLookupWgs = 2048;                           // lookup workgroups to aim for (8 per CU)
 constexpr uint32_t kFinHistBytes = 64u * 1024u;                 // per-subgroup histogram ceiling
@@ -69,9 +68,8 @@ struct PartGeo {
     uint32_t xcd;         // give the workgroups of one slice to one XCD
     uint32_t split;       // lookup workgroups per slice, each over a range of subgroups
     uint32_t span;        // subgroups per range (a multiple of kGroupRuns)
+    uint32_t fgroup;      // subgroups per finalize workgroup
     uint32_t lds_scatter, lds_lookup, lds_final;
-    uint32_t dbits;       // distance bits of a result: values 0..k
-    uint32_t gmul;        // ceil(2^32 / g), v / g = umulhi(v, gmul) for v < 2^16; 0 for g = 1
 };
 
 // Run table: row s (n_slices + 1 cells of 32 bits) belongs to subgroup s.
@@ -92,9 +90,9 @@ __global__ void __launch_bounds__(kRunThreads) k_run_scatter(Geo G, PartGeo PG, 
     const uint32_t nkp = (PG.hosts + 3u) & ~3u;
     uint32_t *cnt = lds;                  // per-slice counts, then cursors
     uint32_t *keys = lds + nsp;           // host keys
-    uint16_t *sorted = reinterpret_cast<uint16_t *>(keys + nkp);   // VAT indices by slice, runs padded to 4
+    uint32_t *sorted = keys + nkp;        // entries by slice, runs padded to 4 (16-byte aligned)
     const uint32_t t = threadIdx.x;
-    const uint32_t mask = (1u << PG.sl) - 1u;
+    const uint32_t sl = PG.sl, mask = (1u << sl) - 1u;
     const uint32_t host_t0 = t / G.g, i_t0 = t - host_t0 * G.g;
     const uint32_t d_ik = PG.dr * kPhi, g_ik = G.g * kPhi;
 
@@ -127,29 +125,28 @@ __global__ void __launch_bounds__(kRunThreads) k_run_scatter(Geo G, PartGeo PG, 
         // only the host advances.  Iterations j < jfull are full for every
         // thread (a uniform branch); the ragged tail is iteration jfull.
         // H(aip, i) = top c bits of the mix (shift = 32 - c is at most 31).
+        // Each VAT's pid stays in a register until it is placed.
         const uint32_t jfull = nv / kRunThreads, tail = nv - jfull * kRunThreads;
-        uint32_t bs[kRunPerThread / 2];    // slices of the thread's VATs, two 16-bit values per word
-#pragma unroll
-        for (uint32_t j = 0; j < kRunPerThread / 2; ++j) bs[j] = 0;
+        uint32_t pid[kRunPerThread];
         if (PG.dr == 0) {
             const uint32_t ik = i_t * kPhi;
 #pragma unroll
             for (uint32_t j = 0; j < kRunPerThread; ++j) {
                 const uint32_t host = host_t + j * PG.dq;
+                pid[j] = 0;
                 if (j < jfull || (j == jfull && t < tail)) {
-                    const uint32_t b = (mix(keys[host] ^ ik) >> G.shift) >> PG.sl;
-                    bs[j >> 1] |= b << ((j & 1u) << 4);
-                    atomicAdd(&cnt[b], 1u);
+                    pid[j] = mix(keys[host] ^ ik) >> G.shift;
+                    atomicAdd(&cnt[pid[j] >> sl], 1u);
                 }
             }
         } else {
             uint32_t host = host_t, i = i_t, ik = i_t * kPhi;
 #pragma unroll
             for (uint32_t j = 0; j < kRunPerThread; ++j) {
+                pid[j] = 0;
                 if (j < jfull || (j == jfull && t < tail)) {
-                    const uint32_t b = (mix(keys[host] ^ ik) >> G.shift) >> PG.sl;
-                    bs[j >> 1] |= b << ((j & 1u) << 4);
-                    atomicAdd(&cnt[b], 1u);
+                    pid[j] = mix(keys[host] ^ ik) >> G.shift;
+                    atomicAdd(&cnt[pid[j] >> sl], 1u);
                 }
                 const bool wrap = i + PG.dr >= G.g;
                 i = i + PG.dr - (wrap ? G.g : 0u);
@@ -184,7 +181,7 @@ __global__ void __launch_bounds__(kRunThreads) k_run_scatter(Geo G, PartGeo PG, 
             const uint32_t c = cnt[b], p = run;
             run += pad4(c);
             cnt[b] = p;
-            for (uint32_t x = p + c; x < run; ++x) sorted[x] = kSortPad;
+            for (uint32_t x = p + c; x < run; ++x) sorted[x] = kRunPad;
         }
         uint32_t total = 0;
         for (uint32_t q = 0; q < kRunThreads / 64; ++q) total += wsum[q];
@@ -196,34 +193,36 @@ __global__ void __launch_bounds__(kRunThreads) k_run_scatter(Geo G, PartGeo PG, 
         if (t == 0) trow[PG.n_slices] = total >> 2;
         __syncthreads();
 
+        // Placement: each VAT's entry (host within subgroup, AT within slice)
+        // at its slice's cursor.
+        if (PG.dr == 0) {
 #pragma unroll
-        for (uint32_t j = 0; j < kRunPerThread; ++j)
-            if (j < jfull || (j == jfull && t < tail)) {
-                const uint32_t slot = atomicAdd(&cnt[(bs[j >> 1] >> ((j & 1u) << 4)) & 0xFFFFu], 1u);
-                sorted[slot] = (uint16_t)(t + j * kRunThreads);
+            for (uint32_t j = 0; j < kRunPerThread; ++j)
+                if (j < jfull || (j == jfull && t < tail)) {
+                    const uint32_t slot = atomicAdd(&cnt[pid[j] >> sl], 1u);
+                    sorted[slot] = ((host_t + j * PG.dq) << sl) | (pid[j] & mask);
+                }
+        } else {
+            uint32_t host = host_t, i = i_t;
+#pragma unroll
+            for (uint32_t j = 0; j < kRunPerThread; ++j) {
+                if (j < jfull || (j == jfull && t < tail)) {
+                    const uint32_t slot = atomicAdd(&cnt[pid[j] >> sl], 1u);
+                    sorted[slot] = (host << sl) | (pid[j] & mask);
+                }
+                const bool wrap = i + PG.dr >= G.g;
+                i = i + PG.dr - (wrap ? G.g : 0u);
+                host += PG.dq + (wrap ? 1u : 0u);
             }
+        }
         __syncthreads();
 
-        // Copy out, one 4-entry chunk per thread and step: each VAT index
-        // becomes its entry (host within subgroup, AT within slice), its pid
-        // hashed again (v / g by a multiply-high: exact for v, g < 2^16).
+        // Copy out as one coalesced stream.
         uint4 *out = reinterpret_cast<uint4 *>(entries + (size_t)s * PG.region);
-        for (uint32_t q = t; q < total / 4; q += kRunThreads) {
-            const uint2 v2 = reinterpret_cast<const uint2 *>(sorted)[q];
-            const uint32_t v[4] = {v2.x & 0xFFFFu, v2.x >> 16, v2.y & 0xFFFFu, v2.y >> 16};
-            uint32_t e[4];
-#pragma unroll
-            for (int m = 0; m < 4; ++m) {
-                const uint32_t host = PG.gmul ? __umulhi(v[m], PG.gmul) : v[m], i = v[m] - host * G.g;
-                const uint32_t pid_m = mix(keys[min(host, PG.hosts - 1u)] ^ (i * kPhi)) >> G.shift;
-                e[m] = v[m] == kSortPad ? kRunPad : (host << PG.sl) | (pid_m & mask);
-            }
-            out[q] = make_uint4(e[0], e[1], e[2], e[3]);
-        }
+        for (uint32_t q = t; q < total / 4; q += kRunThreads) out[q] = reinterpret_cast<const uint4 *>(sorted)[q];
         // Ready the next subgroup: the copy above reads only the sorted
-        // indices and the keys, so both wait for the barrier.
+        // entries, and the keys are not read after the placement.
         for (uint32_t q = t; q < nsp; q += kRunThreads) cnt[q] = 0;
-        __syncthreads();
         if (t < nh_next) keys[t] = host_key(G, aip_next);
         __syncthreads();
     }
@@ -450,35 +449,39 @@ __global__ void __launch_bounds__(kFinThreads, 5) k_run_finalize(Geo G, PartGeo 
                                                              const mlp::Packed *__restrict__ P,
                                                              float *__restrict__ cf_out)
 {
-    // [hosts][rowp] packed 16-bit bins, then the subgroup's run cells and the
-    // prefix of their live entries in 4-entry pieces
+    // [hosts][rowp] packed 16-bit bins of the workgroup's fgroup subgroups,
+    // then their run cells and the prefix of their live entries in 4-entry
+    // pieces (run r is slice r mod n_slices of subgroup s0 + r / n_slices)
     extern __shared__ __attribute__((aligned(16))) uint32_t hist[];
     __shared__ uint32_t wtot[kFinThreads / 64];
-    const uint32_t s = blockIdx.x, t = threadIdx.x;
-    const uint32_t h0 = s * PG.hosts;
-    const uint32_t nh = min(PG.hosts, n - h0);
+    const uint32_t t = threadIdx.x;
+    const uint32_t s0 = blockIdx.x * PG.fgroup;
+    const uint32_t nsg = min(PG.fgroup, PG.n_sub - s0);
+    const uint32_t h0 = s0 * PG.hosts;
+    const uint32_t nh = min(nsg * PG.hosts, n - h0);
     const uint32_t rowp = PG.rowp;
-    const uint32_t ns = PG.n_slices;
-    uint32_t *cell = hist + nh * rowp;          // [ns] run cells
-    uint32_t *pre = cell + ns;                  // [ns + 1] pieces before run b
+    const uint32_t ns = PG.n_slices, nr = nsg * ns;
+    uint32_t *cell = hist + nh * rowp;          // [nr] run cells
+    uint32_t *pre = cell + nr;                  // [nr + 1] pieces before run r
     for (uint32_t q = t; q < nh * rowp; q += kFinThreads) hist[q] = 0;
     // Exclusive prefix of the runs' piece counts: thread t owns runs
-    // [t rs, (t+1) rs).
-    const uint32_t *trow = table + (size_t)s * (ns + 1);
-    const uint32_t rs = (ns + kFinThreads - 1) / kFinThreads;
-    // (a live count never exceeds the run's slots; the clamp keeps every read
-    // inside them whatever the table holds)
-    auto pieces = [&](uint32_t b, uint32_t c) {
-        const uint32_t len = (trow[b + 1] & 0xFFFFu) - (c & 0xFFFFu);
-        return min(((c >> 16) + 3u) >> 2, len);
+    // [t rs, (t+1) rs).  (A live count never exceeds the run's slots; the
+    // clamp keeps every read inside them whatever the table holds.)
+    const uint32_t rs = (nr + kFinThreads - 1) / kFinThreads;
+    auto cell_of = [&](uint32_t r, uint32_t &next) {
+        const uint32_t *trow = table + (size_t)(s0 + r / ns) * (ns + 1);
+        const uint32_t b = r % ns;
+        next = trow[b + 1] & 0xFFFFu;
+        return trow[b];
     };
     uint32_t mine = 0;
     for (uint32_t q = 0; q < rs; ++q) {
-        const uint32_t b = t * rs + q;
-        if (b < ns) {
-            const uint32_t c = trow[b];
-            const uint32_t np = pieces(b, c);
-            cell[b] = (c & 0xFFFFu) | (min(c >> 16, 4u * np) << 16);
+        const uint32_t r = t * rs + q;
+        if (r < nr) {
+            uint32_t next;
+            const uint32_t c = cell_of(r, next);
+            const uint32_t np = min(((c >> 16) + 3u) >> 2, next - (c & 0xFFFFu));
+            cell[r] = (c & 0xFFFFu) | (min(c >> 16, 4u * np) << 16);
             mine += np;
         }
     }
@@ -497,49 +500,66 @@ __global__ void __launch_bounds__(kFinThreads, 5) k_run_finalize(Geo G, PartGeo 
         total += wtot[q];
     }
     for (uint32_t q = 0; q < rs; ++q) {
-        const uint32_t b = t * rs + q;
-        if (b < ns) {
-            pre[b] = run;
-            run += ((cell[b] >> 16) + 3u) >> 2;    // the clamped count's pieces
+        const uint32_t r = t * rs + q;
+        if (r < nr) {
+            pre[r] = run;
+            run += ((cell[r] >> 16) + 3u) >> 2;    // the clamped count's pieces
         }
     }
-    if (t == 0) pre[ns] = total;
+    if (t == 0) pre[nr] = total;
     __syncthreads();
     {
         // Live entries: piece c (up to 4 entries, 16 bytes) belongs to the run
-        // b with pre[b] <= c < pre[b + 1].  Each entry's AT is read from the
+        // r with pre[r] <= c < pre[r + 1].  Each entry's AT is read from the
         // pool for its distance (Eq. 5) and counted into its host's bin with
         // an LDS atomic.  Bin k (inactive) is not counted: it is g minus the
         // others, filled in below.
-        const uint4 *hh = reinterpret_cast<const uint4 *>(hits + (size_t)s * PG.region);
         const uint32_t sl = PG.sl, mask = (1u << sl) - 1u;
         const uint32_t bact0 = st->bact0;
         const uint32_t inact = inactive_value(G);
-        for (uint32_t c = t; c < total; c += kFinThreads) {
-            uint32_t lo = 0, hi = ns;                // largest b with pre[b] <= c
-            while (hi - lo > 1) {
-                const uint32_t mid = (lo + hi) >> 1;
-                if (pre[mid] <= c) lo = mid; else hi = mid;
-            }
-            const uint32_t k4 = c - pre[lo];
-            const uint32_t cb = cell[lo];
-            const uint32_t nr = min(4u, (cb >> 16) - 4u * k4);
-            const uint4 w4 = hh[(cb & 0xFFFFu) + k4];
-            const uint32_t first = lo << sl;
-            uint32_t e[4], v[4];
+        // kFinPieces pieces per thread at a time: their loads, then the pool
+        // reads of their entries, are in flight together.
+        for (uint32_t c0 = t; c0 < total; c0 += kFinPieces * kFinThreads) {
+            uint4 w4[kFinPieces];
+            uint32_t first[kFinPieces], hrow[kFinPieces], nv[kFinPieces];
 #pragma unroll
-            for (uint32_t m = 0; m < 4; ++m) {
-                e[m] = comp4(w4, m);
-                v[m] = m < nr ? load_at<W>(pool, first | (e[m] & mask), G.wb) : inact;
+            for (uint32_t u = 0; u < kFinPieces; ++u) {
+                const uint32_t c = c0 + u * kFinThreads;
+                nv[u] = 0;
+                first[u] = 0;
+                hrow[u] = 0;
+                w4[u] = make_uint4(0u, 0u, 0u, 0u);
+                if (c < total) {
+                    uint32_t lo = 0, hi = nr;                // largest r with pre[r] <= c
+                    while (hi - lo > 1) {
+                        const uint32_t mid = (lo + hi) >> 1;
+                        if (pre[mid] <= c) lo = mid; else hi = mid;
+                    }
+                    const uint32_t k4 = c - pre[lo];
+                    const uint32_t cb = cell[lo];
+                    const uint32_t sg = lo / ns, b = lo - sg * ns;
+                    nv[u] = min(4u, (cb >> 16) - 4u * k4);
+                    first[u] = b << sl;
+                    hrow[u] = sg * PG.hosts;
+                    w4[u] = reinterpret_cast<const uint4 *>(hits + (size_t)(s0 + sg) * PG.region)[(cb & 0xFFFFu) + k4];
+                }
             }
+            uint32_t v[kFinPieces][4];
 #pragma unroll
-            for (uint32_t m = 0; m < 4; ++m) {
-                if (v[m] == inact) continue;
-                const uint32_t pid = first | (e[m] & mask);
-                const uint32_t d = value_dist(G, bact0, pid, v[m]);
-                if (d >= G.k) continue;
-                atomicAdd(&hist[(e[m] >> sl) * rowp + (d >> 1)], 1u << ((d & 1u) << 4));
-            }
+            for (uint32_t u = 0; u < kFinPieces; ++u)
+#pragma unroll
+                for (uint32_t m = 0; m < 4; ++m)
+                    v[u][m] = m < nv[u] ? load_at<W>(pool, first[u] | (comp4(w4[u], m) & mask), G.wb) : inact;
+#pragma unroll
+            for (uint32_t u = 0; u < kFinPieces; ++u)
+#pragma unroll
+                for (uint32_t m = 0; m < 4; ++m) {
+                    if (v[u][m] == inact) continue;
+                    const uint32_t e = comp4(w4[u], m);
+                    const uint32_t d = value_dist(G, bact0, first[u] | (e & mask), v[u][m]);
+                    if (d >= G.k) continue;
+                    atomicAdd(&hist[(hrow[u] + (e >> sl)) * rowp + (d >> 1)], 1u << ((d & 1u) << 4));
+                }
         }
     }
     __syncthreads();
