@@ -942,14 +942,27 @@ static bool part_geo(const vate_sketch *s, uint64_t n, PartGeo *out)
         p.fgroup = best;
     }
     p.lds_scatter = (uint32_t)lds_for(hosts);
-    p.lds_lookup = p.bm_words * 4u;
+    {   // lookup LDS: bits (whole 256-AT blocks + a sentinel word), rank tables,
+        // run counters, then as many live ATs' distances as fit
+        p.bm_words_lds = (p.bm_words + 1u + 7u) & ~7u;
+        const uint32_t nblk = p.bm_words_lds / 8u, nsup = (nblk + 7u) / 8u;
+        const uint32_t fixed = 4u * (p.bm_words_lds + nsup + (nblk + 1u) / 2u + kRunThreads);
+        p.dist16 = G.k > 256 ? 1u : 0u;
+        const uint32_t room = s->lds_budget > fixed ? s->lds_budget - fixed : 0u;
+        p.dist_cap = room >> p.dist16;
+        p.lds_lookup = (fixed + (p.dist_cap << p.dist16) + 15u) & ~15u;
+        if (p.lds_lookup > s->lds_budget) p.lds_lookup = s->lds_budget & ~15u, p.dist_cap = (p.lds_lookup - fixed) >> p.dist16;
+    }
     p.lds_final = p.fgroup * p.hosts * p.rowp * 4u + 8u * p.fgroup * (uint32_t)ns + 4u;
     // Each slice's walk over the subgroups is cut into ranges, one workgroup
-    // each, so that the launch has about kLookupWgs workgroups; a range is a
-    // whole number of 64-subgroup windows (one per wavefront at a time) and
-    // holds at least one window per wavefront.
+    // each, so that the launch has at least one workgroup per CU (each builds
+    // its slice's LDS tables once); a range is a whole number of 64-subgroup
+    // windows (one per wavefront at a time) and holds at least one window
+    // per wavefront.
     const uint32_t per_round = kRunThreads;   // 16 wavefronts x 64 subgroups
-    const uint32_t want = std::max<uint32_t>(1u, std::min<uint32_t>(kLookupWgs / p.n_slices, p.n_sub / per_round));
+    const uint32_t cus = std::max<uint32_t>(1u, s->n_cu);
+    const uint32_t want = std::max<uint32_t>(1u, std::min<uint32_t>((cus + p.n_slices - 1u) / p.n_slices,
+                                                                    p.n_sub / per_round));
     p.span = ((p.n_sub + want - 1u) / want + 63u) & ~63u;
     p.split = (p.n_sub + p.span - 1u) / p.span;
     *out = p;
@@ -960,7 +973,7 @@ static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 struct RunWs {
     uint32_t *entries;          // [n_sub][region] sorted entries
-    uint32_t *hits;             // [n_sub][region] live entries, packed at the front of each run's slots
+    uint32_t *hits;             // [n_sub][region] live results (host << 16 | distance), packed at the front of each run's slots
     uint32_t *table;            // [n_sub][n_slices + 1] run starts and live counts
     unsigned long long *cum;    // [k + 1] census prefix (several windows)
     size_t bytes;
@@ -1009,9 +1022,9 @@ static int launch_part(vate_sketch *s, const PartGeo &pg, void *ws, const uint32
     if (!(attr_set.load(std::memory_order_acquire) & bit)) {
         int rc = set_lds_limit(s, reinterpret_cast<const void *>(&k_run_scatter), s->lds_budget);
         if (rc == VATE_OK)
-            rc = set_lds_limit(s, reinterpret_cast<const void *>(&k_run_lookup), 1u << (kSliceLog2 - 3));
+            rc = set_lds_limit(s, reinterpret_cast<const void *>(&k_run_lookup<W>), s->lds_budget);
         if (rc == VATE_OK)
-            rc = set_lds_limit(s, reinterpret_cast<const void *>(&k_run_finalize<W, MODE>), kFinHistBytes + kFinRunBytes);
+            rc = set_lds_limit(s, reinterpret_cast<const void *>(&k_run_finalize<MODE>), kFinHistBytes + kFinRunBytes);
         if (rc != VATE_OK) return rc;
         attr_set.fetch_or(bit, std::memory_order_release);
     }
@@ -1020,11 +1033,11 @@ static int launch_part(vate_sketch *s, const PartGeo &pg, void *ws, const uint32
         k_run_scatter<<<std::min(pg.n_sub, s->n_cu), kRunThreads, pg.lds_scatter, st>>>(s->G, pg, hosts, n, w.entries,
                                                                                        w.table);
     if (steps == PART_PLAN) return VATE_OK;
-    k_run_lookup<<<pg.n_slices * pg.split, kRunThreads, pg.lds_lookup, st>>>(
-        s->G, pg, reinterpret_cast<const uint32_t *>(s->bitmap), w.entries, w.table, w.hits);
+    k_run_lookup<W><<<pg.n_slices * pg.split, kRunThreads, pg.lds_lookup, st>>>(
+        s->G, pg, s->pool, reinterpret_cast<const uint32_t *>(s->bitmap), s->st, w.entries, w.table, w.hits);
     if (MODE == kFinMulti) k_census_prefix<<<1, 64, 0, st>>>(s->G, s->st, w.cum);
-    k_run_finalize<W, MODE><<<(pg.n_sub + pg.fgroup - 1) / pg.fgroup, kFinThreads, pg.lds_final, st>>>(
-        s->G, pg, s->pool, s->st, n, kprime, w.hits, w.table, est, live, hist, win, w.cum,
+    k_run_finalize<MODE><<<(pg.n_sub + pg.fgroup - 1) / pg.fgroup, kFinThreads, pg.lds_final, st>>>(
+        s->G, pg, s->st, n, kprime, w.hits, w.table, est, live, hist, win, w.cum,
         static_cast<const mlp::Packed *>(weights), cf);
     return VATE_OK;
 }

@@ -45,11 +45,8 @@ constexpr uint32_t kRunLdsStatic = 64u;                         // k_run_scatter
 constexpr uint32_t kSliceLog2 = 20;                             // ATs per slice: 2^20, 128 KiB of activity bits
 constexpr uint32_t kRunMaxSlices = 4096;                        // any pool up to 2^32 ATs
 constexpr uint32_t kRunMaxHosts = 1024;                         // hosts per subgroup
-constexpr uint32_t kRunPad = 0xFFFFFFFFu;                       // padding entry (never a real one: host < 2^12)
 constexpr uint32_t kFinThreads = 256;
-constexpr uint32_t kFinPieces = 4;                              // live-entry pieces a finalize thread has in flight
 constexpr uint32_t kLookU = 8;                                  // 16-byte entry chunks per lane and lookup pass
-constexpr uint32_t kLookupWgs = 2048;                           // lookup workgroups to aim for (8 per CU)
 constexpr uint32_t kFinHistBytes = 64u * 1024u;                 // per-subgroup histogram ceiling
 constexpr uint32_t kFinRunBytes = 8u * (kRunMaxSlices + 1u);    // run cells and chunk prefix in the finalize
 
@@ -57,6 +54,9 @@ struct PartGeo {
     uint32_t sl;          // ATs per slice = 2^sl
     uint32_t n_slices;    // N >> sl
     uint32_t bm_words;    // 32-bit bitmap words per slice (at least one)
+    uint32_t bm_words_lds;// the lookup's LDS words for them: whole 256-AT blocks and a zero sentinel word after
+    uint32_t dist_cap;    // live ATs of a slice whose distances the lookup keeps in LDS
+    uint32_t dist16;      // distances take 16 bits (k > 256)
     uint32_t hosts;       // hosts per subgroup
     uint32_t n_sub;       // subgroups
     uint32_t vats;        // hosts * g
@@ -181,7 +181,7 @@ __global__ void __launch_bounds__(kRunThreads) k_run_scatter(Geo G, PartGeo PG, 
             const uint32_t c = cnt[b], p = run;
             run += pad4(c);
             cnt[b] = p;
-            for (uint32_t x = p + c; x < run; ++x) sorted[x] = kRunPad;
+            for (uint32_t x = p + c; x < run; ++x) sorted[x] = 1u << sl;   // padding: the slice's sentinel bit
         }
         uint32_t total = 0;
         for (uint32_t q = 0; q < kRunThreads / 64; ++q) total += wsum[q];
@@ -200,7 +200,7 @@ __global__ void __launch_bounds__(kRunThreads) k_run_scatter(Geo G, PartGeo PG, 
             for (uint32_t j = 0; j < kRunPerThread; ++j)
                 if (j < jfull || (j == jfull && t < tail)) {
                     const uint32_t slot = atomicAdd(&cnt[pid[j] >> sl], 1u);
-                    sorted[slot] = ((host_t + j * PG.dq) << sl) | (pid[j] & mask);
+                    sorted[slot] = ((host_t + j * PG.dq) << (sl + 1)) | (pid[j] & mask);
                 }
         } else {
             uint32_t host = host_t, i = i_t;
@@ -208,7 +208,7 @@ __global__ void __launch_bounds__(kRunThreads) k_run_scatter(Geo G, PartGeo PG, 
             for (uint32_t j = 0; j < kRunPerThread; ++j) {
                 if (j < jfull || (j == jfull && t < tail)) {
                     const uint32_t slot = atomicAdd(&cnt[pid[j] >> sl], 1u);
-                    sorted[slot] = (host << sl) | (pid[j] & mask);
+                    sorted[slot] = (host << (sl + 1)) | (pid[j] & mask);
                 }
                 const bool wrap = i + PG.dr >= G.g;
                 i = i + PG.dr - (wrap ? G.g : 0u);
@@ -235,53 +235,155 @@ __device__ __forceinline__ uint32_t comp4(const uint4 &v, uint32_t m)
     return m == 0 ? v.x : m == 1 ? v.y : m == 2 ? v.z : v.w;
 }
 
-__global__ void __launch_bounds__(kRunThreads) k_run_lookup(Geo G, PartGeo PG, const uint32_t *__restrict__ bitmap,
+// Rank support for the slice's activity bits in the lookup's LDS: the live
+// ATs before each superblock of 2048 ATs (32 bits) and before each block of
+// 256 ATs within its superblock (16 bits); a live AT's rank is those plus
+// the set bits before it in its block's eight words.
+constexpr uint32_t kBlkLog2 = 8, kSupLog2 = 11;
+
+__device__ __forceinline__ uint32_t live_rank(const uint32_t *bm, const uint32_t *sup, const uint16_t *blk,
+                                              uint32_t o)
+{
+    uint32_t r = sup[o >> kSupLog2] + blk[o >> kBlkLog2];
+    const uint32_t w = o >> 5;
+    for (uint32_t x = w & ~7u; x < w; ++x) r += __popc(bm[x]);
+    return r + __popc(bm[w] & ((1u << (o & 31u)) - 1u));
+}
+
+template <int W>
+__global__ void __launch_bounds__(kRunThreads) k_run_lookup(Geo G, PartGeo PG, const uint8_t *__restrict__ pool,
+                                                           const uint32_t *__restrict__ bitmap,
+                                                           const DevState *__restrict__ st,
                                                            const uint32_t *__restrict__ entries,
                                                            uint32_t *__restrict__ table, uint32_t *__restrict__ hits_out)
 {
-    extern __shared__ __attribute__((aligned(16))) uint32_t bm[];   // the slice's activity bits
+    // LDS: the slice's activity bits (then zero words up to a whole block and
+    // the padding entries' sentinel word), the rank tables, one live-result
+    // counter per run of each wavefront's window, and the distances of the
+    // slice's live ATs in slice order (when they fit).
+    extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
+    __shared__ uint32_t wsum[kRunThreads / 64];
+    const uint32_t sl = PG.sl, mask = (1u << sl) - 1u, omask = (2u << sl) - 1u;
+    const uint32_t nw = PG.bm_words, nwp = PG.bm_words_lds;
+    const uint32_t nblk = nwp / 8u, nsup = (nblk + 7u) / 8u;
+    uint32_t *bm = lds;
+    uint32_t *sup = bm + nwp;
+    uint16_t *blk = reinterpret_cast<uint16_t *>(sup + nsup);
+    uint32_t *rcnt = sup + nsup + (nblk + 1u) / 2u;
+    uint8_t *dist8 = reinterpret_cast<uint8_t *>(rcnt + kRunThreads);
+    uint16_t *dist16 = reinterpret_cast<uint16_t *>(dist8);
+
     uint32_t b, part;
-    if (PG.xcd) {              // workgroup x runs on XCD x mod 8: a slice's workgroups share one L2
+    if (PG.xcd) {              // XCD x mod 8 takes a contiguous range of slices
         const uint32_t r = blockIdx.x & 7u, u = blockIdx.x >> 3;
+        const uint32_t per = PG.n_slices / 8u;
         part = u % PG.split;
-        b = ((u / PG.split) << 3) | r;
+        b = r * per + u / PG.split;
     } else {
         part = blockIdx.x % PG.split;
         b = blockIdx.x / PG.split;
     }
     const uint32_t s_lo = part * PG.span, s_hi = min(PG.n_sub, s_lo + PG.span);
-    const uint32_t mask = (1u << PG.sl) - 1u;
+    const uint32_t t = threadIdx.x, lane = t & 63u, wv = t >> 6;
     {
-        const uint32_t nw = PG.bm_words;
         const uint32_t *src = bitmap + (size_t)b * nw;
-        if ((nw & 3u) == 0) {
-            for (uint32_t q = threadIdx.x; q < nw / 4; q += kRunThreads)
-                reinterpret_cast<uint4 *>(bm)[q] = reinterpret_cast<const uint4 *>(src)[q];
+        for (uint32_t q = t; q < nwp; q += kRunThreads) {
+            uint32_t v = q < nw ? src[q] : 0u;
+            if (sl < 5 && q == 0) v &= (1u << (1u << sl)) - 1u;   // bits past the pool: the sentinel among them
+            bm[q] = v;
+        }
+    }
+    __syncthreads();
+    // rank tables: thread x < nsup sums its superblock's blocks
+    uint32_t stot = 0;
+    if (t < nsup) {
+        for (uint32_t k = 0; k < 8u && 8u * t + k < nblk; ++k) {
+            const uint32_t kb = 8u * t + k;
+            blk[kb] = (uint16_t)stot;
+            for (uint32_t x = 0; x < 8u; ++x) stot += __popc(bm[8u * kb + x]);
+        }
+    }
+    // exclusive scan of the superblock totals (nsup <= kRunThreads)
+    {
+        uint32_t incl = stot;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(incl, off, 64);
+            if (lane >= (uint32_t)off) incl += y;
+        }
+        if (lane == 63) wsum[wv] = incl;
+        __syncthreads();
+        uint32_t run = incl - stot;
+        for (uint32_t q = 0; q < wv; ++q) run += wsum[q];
+        if (t < nsup) sup[t] = run;
+    }
+    uint32_t live = 0;
+    for (uint32_t q = 0; q < kRunThreads / 64; ++q) live += wsum[q];
+    const uint32_t bact0 = st->bact0;
+    const uint32_t inact = inactive_value(G);
+    const uint32_t first = b << sl;      // b < 2^(c - sl): no overflow
+    uint32_t act0 = 0, act1 = 0, split = 0;
+    if (PG.fast) {             // the slice meets block bid0 and at most block bid0 + 1
+        const uint32_t bid0 = block_of(G, first);
+        act0 = block_act(G, bact0, bid0);
+        const uint64_t nxt = block_start(G, bid0 + 1);
+        split = nxt - first > (uint64_t)mask ? mask + 1u : (uint32_t)(nxt - first);
+        act1 = block_act(G, bact0, bid0 + 1 < G.twok ? bid0 + 1 : bid0);
+    }
+    // Distance (Eq. 5) of a live AT at offset o of the slice, from the pool;
+    // its bit says it is active for window k, so d < k.
+    auto dist_at = [&](uint32_t o) -> uint32_t {
+        const uint32_t v = load_at<W>(pool, first | o, G.wb);
+        if (v == inact) return G.k;
+        uint32_t d;
+        if (G.dr) {
+            d = v;
         } else {
-            for (uint32_t q = threadIdx.x; q < nw; q += kRunThreads) bm[q] = src[q];
+            const uint32_t act = PG.fast ? (o < split ? act0 : act1) : block_act(G, bact0, block_of(G, first | o));
+            d = at_dist(G, act, v);
+        }
+        return d < G.k ? d : G.k;
+    };
+    // The distances of the slice's live ATs, in slice order, when they fit
+    // the LDS left over; otherwise each live entry reads its AT from the pool.
+    const bool in_lds = live <= PG.dist_cap;
+    __syncthreads();
+    if (in_lds) {
+        for (uint32_t q = t; q < nw; q += kRunThreads) {
+            uint32_t bits = bm[q];
+            if (!bits) continue;
+            uint32_t r = live_rank(bm, sup, blk, 32u * q);
+            while (bits) {
+                const uint32_t x = __builtin_ctz(bits);
+                bits &= bits - 1u;
+                const uint32_t d = dist_at(32u * q + x);
+                if (PG.dist16) dist16[r] = (uint16_t)d; else dist8[r] = (uint8_t)d;
+                ++r;
+            }
         }
     }
     __syncthreads();
 
-    const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
-    const uint64_t lt = (1ull << lane) - 1ull;
     const uint32_t row = PG.n_slices + 1;
     uint16_t *tab16 = reinterpret_cast<uint16_t *>(table);
     const uint4 *ent4 = reinterpret_cast<const uint4 *>(entries);
     const uint32_t rq = PG.region / 4;
     constexpr uint32_t kPass = 64u * kLookU;
+    uint32_t *cnt = rcnt + 64u * wv;
     // A wavefront takes windows of 64 subgroups (lane r: run r of the
     // window), kRunThreads subgroups apart.  The window's runs in this slice
     // are one flat list of chunks (run after run), read in passes of kLookU
-    // chunks per lane.  A live entry's rank in the flat list minus the rank
-    // of its run's first chunk is its slot among the run's live results.
+    // chunks per lane.  A live entry takes the next slot of its run from an
+    // LDS counter (the order within a run is immaterial: the finalize only
+    // counts), and its distance from LDS.
     for (uint32_t s0 = s_lo + wv * 64u; s0 < s_hi; s0 += kRunThreads) {
         uint32_t Sv = 0, len = 0;      // lane r: start (chunks) and length of run r
-        if (s0 + lane < s_hi) {
+        if (lane < s_hi - s0) {
             const size_t cell = (size_t)(s0 + lane) * row + b;
             Sv = tab16[2 * cell];
             len = (uint32_t)tab16[2 * cell + 2] - Sv;
         }
+        cnt[lane] = 0;
         uint32_t incl = len;
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) {
@@ -290,15 +392,14 @@ __global__ void __launch_bounds__(kRunThreads) k_run_lookup(Geo G, PartGeo PG, c
         }
         const uint32_t Fv = incl - len;                         // run r's first chunk in the flat list
         const uint32_t Ftot = __builtin_amdgcn_readlane(incl, 63);
-        uint32_t Pv = 0;                                        // live entries before run r's first chunk
-        uint32_t hits = 0;                                      // live entries of the window so far
         for (uint32_t base = 0; base < Ftot; base += kPass) {
             uint4 e4[kLookU];
             uint32_t jr[kLookU];
 #pragma unroll
             for (uint32_t q = 0; q < kLookU; ++q) {
                 const uint32_t i0 = base + 64u * q, i = i0 + lane;
-                e4[q] = make_uint4(kRunPad, kRunPad, kRunPad, kRunPad);
+                const uint32_t pad = 1u << sl;
+                e4[q] = make_uint4(pad, pad, pad, pad);
                 jr[q] = 0;
                 if (i0 < Ftot) {
                     // run of chunk i: the last r with F_r <= i (F is nondecreasing,
@@ -317,62 +418,44 @@ __global__ void __launch_bounds__(kRunThreads) k_run_lookup(Geo G, PartGeo PG, c
                     if (i < Ftot) e4[q] = ent4[(size_t)(s0 + j) * rq + Sj + (i - Fj)];
                 }
             }
-            // live bits (CheckAT for window k) of the lane's entries
-            uint64_t M = 0;
+            // live bits (CheckAT for window k); a padding entry reads the
+            // zero sentinel bit
+            uint32_t M = 0;
 #pragma unroll
             for (uint32_t q = 0; q < kLookU; ++q)
 #pragma unroll
                 for (uint32_t m = 0; m < 4; ++m) {
-                    const uint32_t e = comp4(e4[q], m);
-                    const uint32_t o = e & mask;
-                    const uint32_t hit = e != kRunPad ? (bm[o >> 5] >> (o & 31u)) & 1u : 0u;
-                    M |= (uint64_t)hit << (4u * q + m);
+                    const uint32_t o = comp4(e4[q], m) & omask;
+                    M |= ((bm[o >> 5] >> (o & 31u)) & 1u) << (4u * q + m);
                 }
-            // rank of the lane's first live entry per chunk in the flat list
-            uint32_t hb[kLookU];
+            // the live entries, up to four per lane per round (every lane
+            // takes part in the shuffles)
+            while (__ballot(M != 0)) {
 #pragma unroll
-            for (uint32_t q = 0; q < kLookU; ++q) {
-                const uint32_t nib = (uint32_t)(M >> (4u * q)) & 0xFu;
-                uint32_t below = 0, tot = 0;
+                for (int r = 0; r < 4; ++r) {
+                    const bool ok = M != 0;
+                    const uint32_t p = ok ? (uint32_t)__builtin_ctz(M) : 0u;
+                    if (ok) M &= M - 1u;
+                    const uint32_t q = p >> 2, m = p & 3u;
+                    uint4 c4 = e4[0];
+                    uint32_t j = jr[0];
 #pragma unroll
-                for (uint32_t m = 0; m < 4; ++m) {
-                    const uint64_t bal = __ballot((nib >> m) & 1u);
-                    below += (uint32_t)__popcll(bal & lt);
-                    tot += (uint32_t)__popcll(bal);
-                }
-                hb[q] = hits + below;
-                hits += tot;
-            }
-            // runs whose first chunk is in this pass: live entries before it
-            {
-                const uint32_t off = Fv - base, qj = off >> 6, lj = off & 63u;
-                uint32_t v = 0;
-#pragma unroll
-                for (uint32_t q = 0; q < kLookU; ++q) {
-                    const uint32_t t = __shfl(hb[q], (int)lj, 64);
-                    if (q == qj) v = t;
-                }
-                if (Fv >= base && Fv < base + kPass && Fv < Ftot) Pv = v;
-            }
-            // live entries to the front of their run's result slots
-#pragma unroll
-            for (uint32_t q = 0; q < kLookU; ++q) {
-                const uint32_t nib = (uint32_t)(M >> (4u * q)) & 0xFu;
-                const uint32_t Sj = __shfl(Sv, (int)jr[q], 64), Pj = __shfl(Pv, (int)jr[q], 64);
-                if (nib) {
-                    uint32_t *dst = hits_out + (size_t)(s0 + jr[q]) * PG.region + 4u * Sj + (hb[q] - Pj);
-#pragma unroll
-                    for (uint32_t m = 0; m < 4; ++m)
-                        if ((nib >> m) & 1u) *dst++ = comp4(e4[q], m);
+                    for (uint32_t qq = 1; qq < kLookU; ++qq)
+                        if (q == qq) c4 = e4[qq], j = jr[qq];
+                    const uint32_t Sj = __shfl(Sv, (int)j, 64);
+                    if (ok) {
+                        const uint32_t e = comp4(c4, m), o = e & mask;
+                        const uint32_t d = in_lds ? (PG.dist16 ? (uint32_t)dist16[live_rank(bm, sup, blk, o)]
+                                                               : (uint32_t)dist8[live_rank(bm, sup, blk, o)])
+                                                  : dist_at(o);
+                        const uint32_t slot = atomicAdd(&cnt[j], 1u);
+                        hits_out[(size_t)(s0 + j) * PG.region + 4u * Sj + slot] = ((e >> (sl + 1)) << 16) | d;
+                    }
                 }
             }
         }
-        // live count of each run beside its start (the shuffle with every
-        // lane active: a lane reads its neighbour's value)
-        const uint32_t pf = Fv < Ftot ? Pv : hits;
-        const uint32_t pn = __shfl_down(pf, 1, 64);
-        if (s0 + lane < s_hi)
-            tab16[2 * ((size_t)(s0 + lane) * row + b) + 1] = (uint16_t)((lane == 63 ? hits : pn) - pf);
+        // live count of each run beside its start
+        if (lane < s_hi - s0) tab16[2 * ((size_t)(s0 + lane) * row + b) + 1] = (uint16_t)cnt[lane];
     }
 }
 
@@ -437,9 +520,8 @@ __device__ __forceinline__ void learned16(const Geo &G, float occupancy, const u
 // At least 5 wavefronts per SIMD: the network's registers would otherwise
 // hold the streaming pass to 4 (measured 0.64 against 0.58 ms on the 40G
 // workload; 6 would spill).
-template <int W, int MODE>
-__global__ void __launch_bounds__(kFinThreads, 5) k_run_finalize(Geo G, PartGeo PG, const uint8_t *__restrict__ pool,
-                                                             const DevState *__restrict__ st,
+template <int MODE>
+__global__ void __launch_bounds__(kFinThreads, 5) k_run_finalize(Geo G, PartGeo PG, const DevState *__restrict__ st,
                                                              uint32_t n, uint32_t kprime,
                                                              const uint32_t *__restrict__ hits,
                                                              const uint32_t *__restrict__ table, float *__restrict__ est,
@@ -509,57 +591,30 @@ __global__ void __launch_bounds__(kFinThreads, 5) k_run_finalize(Geo G, PartGeo 
     if (t == 0) pre[nr] = total;
     __syncthreads();
     {
-        // Live entries: piece c (up to 4 entries, 16 bytes) belongs to the run
-        // r with pre[r] <= c < pre[r + 1].  Each entry's AT is read from the
-        // pool for its distance (Eq. 5) and counted into its host's bin with
-        // an LDS atomic.  Bin k (inactive) is not counted: it is g minus the
-        // others, filled in below.
-        const uint32_t sl = PG.sl, mask = (1u << sl) - 1u;
-        const uint32_t bact0 = st->bact0;
-        const uint32_t inact = inactive_value(G);
-        // kFinPieces pieces per thread at a time: their loads, then the pool
-        // reads of their entries, are in flight together.
-        for (uint32_t c0 = t; c0 < total; c0 += kFinPieces * kFinThreads) {
-            uint4 w4[kFinPieces];
-            uint32_t first[kFinPieces], hrow[kFinPieces], nv[kFinPieces];
-#pragma unroll
-            for (uint32_t u = 0; u < kFinPieces; ++u) {
-                const uint32_t c = c0 + u * kFinThreads;
-                nv[u] = 0;
-                first[u] = 0;
-                hrow[u] = 0;
-                w4[u] = make_uint4(0u, 0u, 0u, 0u);
-                if (c < total) {
-                    uint32_t lo = 0, hi = nr;                // largest r with pre[r] <= c
-                    while (hi - lo > 1) {
-                        const uint32_t mid = (lo + hi) >> 1;
-                        if (pre[mid] <= c) lo = mid; else hi = mid;
-                    }
-                    const uint32_t k4 = c - pre[lo];
-                    const uint32_t cb = cell[lo];
-                    const uint32_t sg = lo / ns, b = lo - sg * ns;
-                    nv[u] = min(4u, (cb >> 16) - 4u * k4);
-                    first[u] = b << sl;
-                    hrow[u] = sg * PG.hosts;
-                    w4[u] = reinterpret_cast<const uint4 *>(hits + (size_t)(s0 + sg) * PG.region)[(cb & 0xFFFFu) + k4];
-                }
+        // Live results: piece c (up to 4 results, 16 bytes: host within its
+        // subgroup << 16 | distance) belongs to the run r with pre[r] <= c <
+        // pre[r + 1]; each is counted into its host's bin with an LDS atomic.
+        // Bin k (inactive) is not counted: it is g minus the others, filled
+        // in below.
+        for (uint32_t c = t; c < total; c += kFinThreads) {
+            uint32_t lo = 0, hi = nr;                // largest r with pre[r] <= c
+            while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (pre[mid] <= c) lo = mid; else hi = mid;
             }
-            uint32_t v[kFinPieces][4];
+            const uint32_t k4 = c - pre[lo];
+            const uint32_t cb = cell[lo];
+            const uint32_t sg = lo / ns;
+            const uint32_t nv = min(4u, (cb >> 16) - 4u * k4);
+            const uint4 w4 = reinterpret_cast<const uint4 *>(hits + (size_t)(s0 + sg) * PG.region)[(cb & 0xFFFFu) + k4];
+            const uint32_t hrow = sg * PG.hosts;
 #pragma unroll
-            for (uint32_t u = 0; u < kFinPieces; ++u)
-#pragma unroll
-                for (uint32_t m = 0; m < 4; ++m)
-                    v[u][m] = m < nv[u] ? load_at<W>(pool, first[u] | (comp4(w4[u], m) & mask), G.wb) : inact;
-#pragma unroll
-            for (uint32_t u = 0; u < kFinPieces; ++u)
-#pragma unroll
-                for (uint32_t m = 0; m < 4; ++m) {
-                    if (v[u][m] == inact) continue;
-                    const uint32_t e = comp4(w4[u], m);
-                    const uint32_t d = value_dist(G, bact0, first[u] | (e & mask), v[u][m]);
-                    if (d >= G.k) continue;
-                    atomicAdd(&hist[(hrow[u] + (e >> sl)) * rowp + (d >> 1)], 1u << ((d & 1u) << 4));
-                }
+            for (uint32_t m = 0; m < 4; ++m) {
+                if (m >= nv) break;
+                const uint32_t r = comp4(w4, m), d = r & 0xFFFFu;
+                if (d >= G.k) continue;
+                atomicAdd(&hist[(hrow + (r >> 16)) * rowp + (d >> 1)], 1u << ((d & 1u) << 4));
+            }
         }
     }
     __syncthreads();
