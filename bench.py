@@ -301,7 +301,7 @@ def blocked_leg(dev, slices, hosts, held_independent, block_log2: int = 6, steps
             with_hist.append(ev[1].elapsed_time(ev[2]))
     del sk
     torch.cuda.empty_cache()
-    bg = T.background(4, dev)
+    bg = T.background(T.BG_SLICES, dev)
     held = T.generate(T.HELD_OUT_SEEDS[:2], bg, device=dev, block_log2=block_log2)
     return {"block_log2": block_log2, "hosts": hosts.numel(),
             "estimate_ms": float(np.median(direct)), "estimate_ms_with_histogram": float(np.median(with_hist)),
@@ -364,6 +364,8 @@ def main() -> int:
         theta = T.init_theta(0, dev)
         weights_src = "untrained (zero output layer: equals the closed form)"
     weights = L.pack(theta, L.new_weights(dev))
+    envelope = T.load_envelope() if os.path.exists(T.WEIGHTS) else None
+    L.set_envelope(weights, envelope)      # hosts outside the training envelope get the closed form
     L.learned_workspace(sk, pop.n_hosts)
     torch.cuda.synchronize()
 
@@ -399,6 +401,7 @@ def main() -> int:
             log(f"[bench] slice {s + 1} of {preroll + args.warmup} untimed")
     torch.cuda.synchronize()
     first = preroll + args.warmup
+    L.fallbacks(weights, reset=True)
     events = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
     log(f"[bench] timing {args.steps} steps (slices {first}..{first + args.steps - 1})")
     torch.cuda.synchronize()
@@ -407,6 +410,7 @@ def main() -> int:
         step(first + i, events[i])
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    fell = L.fallbacks(weights, reset=True)
     ingest_ms = np.mean([e[0].elapsed_time(e[1]) for e in events])
     census_ms = np.mean([e[1].elapsed_time(e[2]) for e in events])
     est_ms = np.mean([e[2].elapsed_time(e[3]) for e in events])
@@ -492,15 +496,22 @@ def main() -> int:
         "update": update,
         "planned_hosts": planned,
         "real_time_margin": 1000.0 / ms_per_step,    # 1 s slices (Sec. 5's real-time criterion)
+        "learned_fallback": {"hosts_per_slice": fell / args.steps,
+                             "fraction": fell / (args.steps * pop.n_hosts),
+                             "envelope": None if envelope is None else
+                             {"k": envelope["k"], "g": envelope["g"], "log2_pool": envelope["log2_pool"],
+                              "width": envelope["width"]},
+                             "note": "hosts of the timed slices given the closed form because a feature "
+                                     "lies outside the network's training range"},
         "roofline": roofline,
     }
     held = None
     if not args.no_eval:
         log("[bench] learned vs closed form on held-out probe episodes")
-        bg = T.background(4, dev)
+        bg = T.background(T.BG_SLICES, dev)
         held = T.generate(T.HELD_OUT_SEEDS[:2], bg, device=dev)
         line["learned_vs_closed_form"] = {"weights": weights_src,
-                                          **T.evaluate(theta, held, device=dev)}
+                                          **T.evaluate(theta, held, device=dev, env=envelope)}
         del bg
     if not args.no_blocked and held is not None:
         log("[bench] locality-blocked H (opt-in variant)")

@@ -41,10 +41,36 @@ extern "C" {
 #define VATE_MLP_FEATURES 64
 #define VATE_MLP_HIDDEN 64
 #define VATE_MLP_PARAMS 8385        /* 64*64 + 64 + 64*64 + 64 + 64 + 1 */
-#define VATE_MLP_WEIGHT_BYTES 25600
+#define VATE_MLP_WEIGHT_BYTES 26368       /* packed network + its training envelope */
 
-/* Pack theta (FP32) into the BF16 inference/training weight layout. */
+/* Pack theta (FP32) into the BF16 inference/training weight layout.  Packing
+ * switches the training envelope (below) off. */
 int vate_mlp_pack(const float *theta_dev, void *weights_dev, void *stream);
+
+/* The envelope the network was trained in: the sketch geometry of its
+ * training states and the range of every feature over them (BF16-rounded
+ * values, as the network sees them).  With an envelope set on the weights,
+ * the learned estimate entry points return the closed form of Eq. 11
+ *   - for every host, when the sketch's k, g, log2_pool or width differs
+ *     from the envelope's (the features then mean something else), and
+ *   - for a host any of whose features lies outside [lo[f], hi[f]],
+ * and count those hosts (plus hosts whose network output is not finite) in a
+ * device counter kept with the weights. */
+typedef struct vate_mlp_envelope {
+    uint32_t k, g, log2_pool, width;
+    float lo[VATE_MLP_FEATURES];
+    float hi[VATE_MLP_FEATURES];
+} vate_mlp_envelope;
+
+/* Set (env non-NULL) or clear (env NULL) the envelope of packed weights and
+ * zero their fallback counter.  Synchronises `stream`, then copies; env is
+ * read during the call only.  Errors: VATE_E_INVAL, VATE_E_DEVICE. */
+int vate_mlp_set_envelope(void *weights_dev, const vate_mlp_envelope *env, void *stream);
+
+/* Hosts given the closed form by the envelope (or a non-finite network
+ * output) since the counter was last zeroed; reset != 0 zeroes it.
+ * Synchronises `stream`.  Errors: VATE_E_INVAL, VATE_E_DEVICE. */
+int vate_mlp_fallbacks(const void *weights_dev, uint64_t *count, int reset, void *stream);
 
 /* o[i] = network(x_i) + r[i] for n feature rows (inference). */
 int vate_mlp_forward(const void *weights_dev, const uint16_t *x_dev, const float *r_dev,
@@ -77,7 +103,8 @@ int vate_mlp_features(const uint32_t *hist_dev, const float *est_dev, size_t n, 
 /* Estimate n_hosts hosts at window k with the learned estimator fused into
  * the gather of vate_estimate (one pass over the VATs): est_cf_dev receives
  * the closed-form estimates, est_dev the learned ones (the closed form where
- * the network's output is not finite).  Requires a closed slice and
+ * the network's output is not finite, and where the weights' envelope rules
+ * the network out).  Requires a closed slice and
  * k + 3 <= 64.  Errors as vate_estimate, VATE_E_UNSUPPORTED for k > 61. */
 int vate_estimate_learned(vate_sketch *s, const uint32_t *hosts_dev, size_t n_hosts,
                           const void *weights_dev, float *est_dev, float *est_cf_dev,

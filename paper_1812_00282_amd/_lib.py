@@ -84,6 +84,17 @@ _SIGS = {
 }
 
 
+class VateMlpEnvelope(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_uint32), ("g", ctypes.c_uint32), ("log2_pool", ctypes.c_uint32),
+                ("width", ctypes.c_uint32), ("lo", ctypes.c_float * 64), ("hi", ctypes.c_float * 64)]
+
+
+_SIGS.update({
+    "vate_mlp_set_envelope": (_i32, [_vp, ctypes.POINTER(VateMlpEnvelope), _vp]),
+    "vate_mlp_fallbacks": (_i32, [_vp, ctypes.POINTER(_u64), _i32, _vp]),
+})
+
+
 class VateBatchTune(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint32) for n in
                 ("ingest_tile", "census_tile", "estimate_block", "grid_preserve",
@@ -108,7 +119,7 @@ _SIGS.update({
 MLP_FEATURES = 64
 MLP_HIDDEN = 64
 MLP_PARAMS = 8385
-MLP_WEIGHT_BYTES = 25600
+MLP_WEIGHT_BYTES = 26368
 NOALLOC_SCRATCH_BYTES = 64 << 20
 
 _lib = None

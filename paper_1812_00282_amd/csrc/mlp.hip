@@ -46,7 +46,11 @@ __global__ void k_pack(const float *__restrict__ theta, Packed *__restrict__ P)
             P->b2[i] = theta[OFF_B2 + i];
             P->w3[i] = theta[OFF_W3 + i];
         }
-        if (threadIdx.x == 0) P->b3 = theta[OFF_B3];
+        if (threadIdx.x == 0) {
+            P->b3 = theta[OFF_B3];
+            P->env.magic = 0;         // packing switches the envelope off
+            P->env.fallbacks = 0;
+        }
     }
 }
 
@@ -305,6 +309,43 @@ int vate_mlp_pack(const float *theta_dev, void *weights_dev, void *stream)
     if (!theta_dev || !weights_dev || (reinterpret_cast<uintptr_t>(weights_dev) & 255u)) return VATE_E_INVAL;
     k_pack<<<16, 256, 0, static_cast<hipStream_t>(stream)>>>(theta_dev, static_cast<Packed *>(weights_dev));
     return mlp_check("pack");
+}
+
+int vate_mlp_set_envelope(void *weights_dev, const vate_mlp_envelope *env, void *stream)
+{
+    if (!weights_dev || (reinterpret_cast<uintptr_t>(weights_dev) & 255u)) return VATE_E_INVAL;
+    Envelope e{};
+    if (env) {
+        for (int f = 0; f < F; ++f)
+            if (!(env->lo[f] <= env->hi[f])) return VATE_E_INVAL;
+        e.magic = kEnvMagic;
+        e.k = env->k;
+        e.g = env->g;
+        e.log2_pool = env->log2_pool;
+        e.width = env->width;
+        for (int f = 0; f < F; ++f) e.lo[f] = env->lo[f], e.hi[f] = env->hi[f];
+    }
+    Packed *P = static_cast<Packed *>(weights_dev);
+    hipError_t err = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+    if (err == hipSuccess) err = hipMemcpy(&P->env, &e, sizeof(Envelope), hipMemcpyHostToDevice);
+    return err == hipSuccess ? VATE_OK : VATE_E_DEVICE;
+}
+
+int vate_mlp_fallbacks(const void *weights_dev, uint64_t *count, int reset, void *stream)
+{
+    if (!weights_dev || !count || (reinterpret_cast<uintptr_t>(weights_dev) & 255u)) return VATE_E_INVAL;
+    const Packed *P = static_cast<const Packed *>(weights_dev);
+    unsigned long long c = 0;
+    hipError_t err = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+    if (err == hipSuccess) err = hipMemcpy(&c, &P->env.fallbacks, sizeof(c), hipMemcpyDeviceToHost);
+    if (err == hipSuccess && reset) {
+        const unsigned long long zero = 0;
+        err = hipMemcpy(const_cast<unsigned long long *>(&P->env.fallbacks), &zero, sizeof(zero),
+                        hipMemcpyHostToDevice);
+    }
+    if (err != hipSuccess) return VATE_E_DEVICE;
+    *count = c;
+    return VATE_OK;
 }
 
 int vate_mlp_forward(const void *weights_dev, const uint16_t *x_dev, const float *r_dev, size_t n, float *o_dev,

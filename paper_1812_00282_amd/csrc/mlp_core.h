@@ -30,6 +30,18 @@ constexpr int OFF_W3 = OFF_B2 + HD;
 constexpr int OFF_B3 = OFF_W3 + HD;
 static_assert(OFF_B3 + 1 == VATE_MLP_PARAMS, "parameter count");
 
+// The network's training envelope (vate_mlp_envelope) as kept with the
+// packed weights, plus the count of hosts it sent to the closed form.
+constexpr uint32_t kEnvMagic = 0x31564E45u;   // set by vate_mlp_set_envelope; anything else: no envelope
+struct Envelope {
+    uint32_t magic;
+    uint32_t k, g, log2_pool, width;
+    uint32_t pad[3];
+    unsigned long long fallbacks;
+    unsigned long long pad2;
+    float lo[F], hi[F];
+};
+
 // Packed inference weights (bytes).
 struct Packed {
     uint16_t W1b[HD * F];     // bf16, row = hidden unit, col = input
@@ -37,8 +49,34 @@ struct Packed {
     uint16_t W2bT[HD * HD];   // transpose of W2b
     float b1[HD], b2[HD], w3[HD], b3;
     float pad[63];
+    Envelope env;
+    float pad3[52];
 };
 static_assert(sizeof(Packed) == VATE_MLP_WEIGHT_BYTES, "packed weight size");
+
+// Whether an envelope is set, and whether it rules the network out for the
+// whole sketch (another geometry).
+__device__ __forceinline__ bool env_on(const Packed *P) { return P->env.magic == kEnvMagic; }
+
+__device__ __forceinline__ bool env_geometry_off(const Packed *P, uint32_t k, uint32_t g, uint32_t c, uint32_t w)
+{
+    return env_on(P) && (P->env.k != k || P->env.g != g || P->env.log2_pool != c || P->env.width != w);
+}
+
+// Whether feature f with BF16 bits xb lies outside the envelope (false
+// without one).
+__device__ __forceinline__ bool env_outside(const Packed *P, int f, uint16_t xb)
+{
+    if (!env_on(P)) return false;
+    const float x = __uint_as_float((uint32_t)xb << 16);
+    return !(x >= P->env.lo[f] && x <= P->env.hi[f]);
+}
+
+// Adds n hosts to the envelope's fallback count (one lane per call).
+__device__ __forceinline__ void env_count(const Packed *P, uint32_t n)
+{
+    if (n) atomicAdd(&const_cast<Packed *>(P)->env.fallbacks, (unsigned long long)n);
+}
 
 // FP32 -> BF16 bits, round to nearest even (finite inputs).
 __device__ __forceinline__ uint16_t bf16_bits(float f)

@@ -569,8 +569,12 @@ __global__ void __launch_bounds__(256) k_estimate_learned(Geo G, const uint8_t *
     const int q = lane >> 4, c = lane & 15;
     uint16_t *xs = xs_all[wave];
     __syncthreads();
+    const bool geo_off = mlp::env_geometry_off(P, G.k, G.g, G.c, G.wb);
     for (int t = 0; t < 4; ++t) {
-        // features of hosts 16t .. 16t+15 of this wavefront (row m = host - 16t)
+        // features of hosts 16t .. 16t+15 of this wavefront (row m = host - 16t);
+        // lane f builds feature f of a row, so one ballot per row says whether
+        // the host is outside the network's envelope
+        uint32_t outside = geo_off ? 0xFFFFu : 0u;
         for (int e = lane; e < 16 * VATE_MLP_FEATURES; e += 64) {
             const int m = e >> 6, f = e & 63, host = 16 * t + m;
             float x = 0.f;
@@ -582,7 +586,9 @@ __global__ void __launch_bounds__(256) k_estimate_learned(Geo G, const uint8_t *
                 x = occupancy;
             else if (f == (int)G.k + 2)
                 x = logf(fmaxf(cf_all[wave][host], 1.0f)) * 0.0625f;
-            xs[m * mlp::LDS_STRIDE + f] = mlp::bf16_bits(x);
+            const uint16_t xb = mlp::bf16_bits(x);
+            xs[m * mlp::LDS_STRIDE + f] = xb;
+            if (__ballot(mlp::env_outside(P, f, xb))) outside |= 1u << m;
         }
         __syncthreads();
         float r4[4];
@@ -591,14 +597,18 @@ __global__ void __launch_bounds__(256) k_estimate_learned(Geo G, const uint8_t *
         mlp::f32x4 z1[4], z2[4];
         float a2v[4][4], o4[4];
         mlp::forward16(P, xs, a1_all[wave], r4, z1, z2, a2v, o4);
+        bool fell = false;
         if (c < 4) {
             const int host = 16 * t + 4 * q + c;
             const uint32_t hg = blockIdx.x * blockDim.x + wave * 64 + host;
             if (hg < n) {
                 const float e = expf(o4[c]);
-                est_out[hg] = isfinite(e) ? e : cf_all[wave][host];
+                fell = ((outside >> (4 * q + c)) & 1u) || !isfinite(e);
+                est_out[hg] = fell ? cf_all[wave][host] : e;
             }
         }
+        const uint64_t fb = __ballot(fell);
+        if (lane == 0) mlp::env_count(P, (uint32_t)__popcll(fb));
         __syncthreads();
     }
 }

@@ -119,14 +119,12 @@ __global__ void __launch_bounds__(kRunThreads) k_run_scatter(Geo G, PartGeo PG, 
         uint32_t host_t = host_t0, i_t = i_t0;
         asm volatile("" : "+v"(host_t), "+v"(i_t));
 
-        // VAT v = t + j * kRunThreads of the subgroup is VAT i = v mod g of
-        // host v / g.  H's multiplier i * phi is carried along (mod 2^32);
-        // when g divides the workgroup size, i (and i * phi) stay fixed and
-        // only the host advances.  Iterations j < jfull are full for every
-        // thread (a uniform branch); the ragged tail is iteration jfull.
-        // H(aip, i) = top c bits of the mix (shift = 32 - c is at most 31).
-        // Each VAT's pid stays in a register until it is placed.
-        const uint32_t jfull = nv / kRunThreads, tail = nv - jfull * kRunThreads;
+        // VAT v = t + j * kRunThreads (v < nv) of the subgroup is VAT
+        // i = v mod g of host v / g.  H's multiplier i * phi is carried along
+        // (mod 2^32); when g divides the workgroup size, i (and i * phi) stay
+        // fixed and only the host advances.  H(aip, i) = top c bits of the
+        // mix (shift = 32 - c is at most 31).  Each VAT's pid stays in a
+        // register until it is placed.
         uint32_t pid[kRunPerThread];
         if (PG.dr == 0) {
             const uint32_t ik = i_t * kPhi;
@@ -134,7 +132,7 @@ __global__ void __launch_bounds__(kRunThreads) k_run_scatter(Geo G, PartGeo PG, 
             for (uint32_t j = 0; j < kRunPerThread; ++j) {
                 const uint32_t host = host_t + j * PG.dq;
                 pid[j] = 0;
-                if (j < jfull || (j == jfull && t < tail)) {
+                if (t + j * kRunThreads < nv) {
                     pid[j] = mix(keys[host] ^ ik) >> G.shift;
                     atomicAdd(&cnt[pid[j] >> sl], 1u);
                 }
@@ -144,7 +142,7 @@ __global__ void __launch_bounds__(kRunThreads) k_run_scatter(Geo G, PartGeo PG, 
 #pragma unroll
             for (uint32_t j = 0; j < kRunPerThread; ++j) {
                 pid[j] = 0;
-                if (j < jfull || (j == jfull && t < tail)) {
+                if (t + j * kRunThreads < nv) {
                     pid[j] = mix(keys[host] ^ ik) >> G.shift;
                     atomicAdd(&cnt[pid[j] >> sl], 1u);
                 }
@@ -198,7 +196,7 @@ __global__ void __launch_bounds__(kRunThreads) k_run_scatter(Geo G, PartGeo PG, 
         if (PG.dr == 0) {
 #pragma unroll
             for (uint32_t j = 0; j < kRunPerThread; ++j)
-                if (j < jfull || (j == jfull && t < tail)) {
+                if (t + j * kRunThreads < nv) {
                     const uint32_t slot = atomicAdd(&cnt[pid[j] >> sl], 1u);
                     sorted[slot] = ((host_t + j * PG.dq) << (sl + 1)) | (pid[j] & mask);
                 }
@@ -206,7 +204,7 @@ __global__ void __launch_bounds__(kRunThreads) k_run_scatter(Geo G, PartGeo PG, 
             uint32_t host = host_t, i = i_t;
 #pragma unroll
             for (uint32_t j = 0; j < kRunPerThread; ++j) {
-                if (j < jfull || (j == jfull && t < tail)) {
+                if (t + j * kRunThreads < nv) {
                     const uint32_t slot = atomicAdd(&cnt[pid[j] >> sl], 1u);
                     sorted[slot] = (host << (sl + 1)) | (pid[j] & mask);
                 }
@@ -426,13 +424,14 @@ __global__ void __launch_bounds__(kRunThreads) k_run_lookup(Geo G, PartGeo PG, c
 #pragma unroll
                 for (uint32_t m = 0; m < 4; ++m) {
                     const uint32_t o = comp4(e4[q], m) & omask;
-                    M |= ((bm[o >> 5] >> (o & 31u)) & 1u) << (4u * q + m);
+                    M |= __builtin_amdgcn_ubfe(bm[o >> 5], o, 1u) << (4u * q + m);   // bit o mod 32
                 }
             // the live entries, up to four per lane per round (every lane
             // takes part in the shuffles)
             while (__ballot(M != 0)) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
+                    if (r > 0 && !__ballot(M != 0)) break;   // a round only while some lane has one left
                     const bool ok = M != 0;
                     const uint32_t p = ok ? (uint32_t)__builtin_ctz(M) : 0u;
                     if (ok) M &= M - 1u;
@@ -486,6 +485,9 @@ __device__ __forceinline__ void learned16(const Geo &G, float occupancy, const u
 {
     const int l = threadIdx.x & 63, q = l >> 4, c = l & 15;
     const float fg = (float)G.g;
+    // Row m (host m) is built by the whole wavefront, lane f = feature f, so
+    // one ballot per row says whether the host is outside the envelope.
+    uint32_t outside = mlp::env_geometry_off(P, G.k, G.g, G.c, G.wb) ? 0xFFFFu : 0u;
     for (int e = l; e < 16 * VATE_MLP_FEATURES; e += 64) {
         const int m = e >> 6, f = e & 63;
         float x = 0.f;
@@ -499,7 +501,9 @@ __device__ __forceinline__ void learned16(const Geo &G, float occupancy, const u
             else if (f == (int)G.k + 2)
                 x = logf(fmaxf(cf16[m], 1.0f)) * 0.0625f;
         }
-        xs[m * mlp::LDS_STRIDE + f] = mlp::bf16_bits(x);
+        const uint16_t xb = mlp::bf16_bits(x);
+        xs[m * mlp::LDS_STRIDE + f] = xb;
+        if (__ballot(mlp::env_outside(P, f, xb))) outside |= 1u << m;
     }
     __syncthreads();
     float r4[4];
@@ -508,13 +512,17 @@ __device__ __forceinline__ void learned16(const Geo &G, float occupancy, const u
     mlp::f32x4 z1[4], z2[4];
     float a2v[4][4], o4[4];
     mlp::forward16(P, xs, a1, r4, z1, z2, a2v, o4);
+    bool fell = false;
     if (c < 4) {
         const uint32_t m = 4 * q + c;
         if (m < n16) {
             const float ex = expf(o4[c]);
-            est[m] = isfinite(ex) ? ex : cf16[m];
+            fell = ((outside >> m) & 1u) || !isfinite(ex);
+            est[m] = fell ? cf16[m] : ex;
         }
     }
+    const uint64_t fb = __ballot(fell);
+    if (l == 0) mlp::env_count(P, (uint32_t)__popcll(fb));
 }
 
 // At least 5 wavefronts per SIMD: the network's registers would otherwise

@@ -11,7 +11,7 @@ import ctypes
 import numpy as np
 import torch
 
-from ._lib import MLP_FEATURES, MLP_PARAMS, MLP_WEIGHT_BYTES, check, lib
+from ._lib import MLP_FEATURES, MLP_PARAMS, MLP_WEIGHT_BYTES, VateMlpEnvelope, check, lib
 from .sketch import Sketch, _stream_handle, as_u32_tensor
 
 OFFSETS = {"W1": (0, (64, 64)), "b1": (4096, (64,)), "W2": (4160, (64, 64)),
@@ -45,6 +45,27 @@ def new_weights(device="cuda") -> torch.Tensor:
 def pack(theta: torch.Tensor, weights: torch.Tensor, stream=None) -> torch.Tensor:
     check(lib().vate_mlp_pack(theta.data_ptr(), weights.data_ptr(), _stream_handle(stream)))
     return weights
+
+
+def set_envelope(weights: torch.Tensor, env: dict | None, stream=None) -> torch.Tensor:
+    """Set the network's training envelope on packed weights (None clears it):
+    env = {"k", "g", "log2_pool", "width", "lo": 64 floats, "hi": 64 floats}.
+    Zeroes the fallback counter."""
+    if env is None:
+        check(lib().vate_mlp_set_envelope(weights.data_ptr(), None, _stream_handle(stream)))
+        return weights
+    e = VateMlpEnvelope(int(env["k"]), int(env["g"]), int(env["log2_pool"]), int(env["width"]),
+                        (ctypes.c_float * 64)(*np.asarray(env["lo"], dtype=np.float32).tolist()),
+                        (ctypes.c_float * 64)(*np.asarray(env["hi"], dtype=np.float32).tolist()))
+    check(lib().vate_mlp_set_envelope(weights.data_ptr(), ctypes.byref(e), _stream_handle(stream)))
+    return weights
+
+
+def fallbacks(weights: torch.Tensor, reset: bool = False, stream=None) -> int:
+    """Hosts the envelope (or a non-finite output) sent to the closed form."""
+    c = ctypes.c_uint64()
+    check(lib().vate_mlp_fallbacks(weights.data_ptr(), ctypes.byref(c), int(reset), _stream_handle(stream)))
+    return c.value
 
 
 def forward(weights, x: torch.Tensor, r: torch.Tensor, out=None, stream=None) -> torch.Tensor:

@@ -34,6 +34,9 @@ from .sketch import Config, Sketch
 HERE = os.path.dirname(os.path.abspath(__file__))
 WEIGHTS = os.path.join(HERE, "weights", "learned_40G_k60_g1024.npz")
 HELD_OUT_SEEDS = list(range(50, 60))
+# Distinct 40 Gb/s background slices the episodes cycle through: at least the
+# window k = 60, so the pool's occupancy reaches that of the stream itself.
+BG_SLICES = 64
 BUCKETS = [(1, 100), (100, 5000), (5000, float("inf"))]
 
 
@@ -53,11 +56,15 @@ class StateSet:
         return self.x.shape[0]
 
 
-def background(n_slices: int, device) -> list[torch.Tensor]:
+def background(n_slices: int = BG_SLICES, device="cuda") -> list[torch.Tensor]:
+    """Slices 1000.. of the 40 Gb/s stream on the device (drawn by threads)."""
+    from concurrent.futures import ThreadPoolExecutor
+
     wl = streams.LINK40G
     pop = wl.population()
-    return [torch.from_numpy(wl.slice(pop, 1000 + s).view(np.int32)).to(device)
-            for s in range(n_slices)]
+    with ThreadPoolExecutor(max(1, min(16, os.cpu_count() or 1))) as ex:
+        host = list(ex.map(lambda s: wl.slice(pop, 1000 + s), range(n_slices)))
+    return [torch.from_numpy(h.view(np.int32)).to(device) for h in host]
 
 
 def generate(seeds, bg, k=60, g=1024, log2_pool=28, n_slices=100, t0=8, device="cuda",
@@ -153,14 +160,30 @@ def closed_form_error(data: StateSet) -> dict:
     return out
 
 
-def evaluate(theta: torch.Tensor, data: StateSet, device="cuda") -> dict:
+def outside_envelope(data: StateSet, env: dict) -> torch.Tensor:
+    """States with a feature outside the envelope's range (the rule the
+    learned estimate kernels apply per host)."""
+    xi = ((data.x.to(torch.int64) & 0xFFFF) << 16).to(torch.int32)
+    xf = xi.view(torch.float32)
+    lo = torch.from_numpy(np.asarray(env["lo"], dtype=np.float32)).to(xf.device)
+    hi = torch.from_numpy(np.asarray(env["hi"], dtype=np.float32)).to(xf.device)
+    return ((xf < lo) | (xf > hi)).any(dim=1)
+
+
+def evaluate(theta: torch.Tensor, data: StateSet, device="cuda", env: dict | None = None) -> dict:
+    """Mean relative errors of the network and of the closed form; with an
+    envelope, states outside it take the closed form, as when served."""
     w = L.pack(theta, L.new_weights(device))
     o = L.forward(w, data.x, data.r)
     est = torch.exp(o.double())
     est = torch.where(torch.isfinite(est), est, data.cf.double())
+    out = {"states": len(data)}
+    if env is not None:
+        off = outside_envelope(data, env)
+        est = torch.where(off, data.cf.double(), est)
+        out["outside_envelope"] = int(off.sum().item())
     tr = data.truth.double()
     cf = data.cf.double()
-    out = {"states": len(data)}
 
     def mre(e, sel):
         return float((torch.abs(e[sel] - tr[sel]) / tr[sel]).mean().item()) if sel.any() else None
@@ -177,9 +200,23 @@ def evaluate(theta: torch.Tensor, data: StateSet, device="cuda") -> dict:
     return out
 
 
-def save(theta: torch.Tensor, path: str, meta: dict) -> None:
+def envelope_of(data: StateSet, k=60, g=1024, log2_pool=28, width=8) -> dict:
+    """The training envelope: the sketch geometry and every feature's range
+    over the states (the BF16 values the network reads)."""
+    xi = ((data.x.to(torch.int64) & 0xFFFF) << 16).to(torch.int32)
+    xf = xi.view(torch.float32)
+    return {"k": k, "g": g, "log2_pool": log2_pool, "width": width,
+            "lo": xf.min(0).values.cpu().numpy().astype(np.float32),
+            "hi": xf.max(0).values.cpu().numpy().astype(np.float32)}
+
+
+def save(theta: torch.Tensor, path: str, meta: dict, env: dict | None = None) -> None:
     os.makedirs(os.path.dirname(path), exist_ok=True)
-    np.savez(path, theta=theta.detach().cpu().numpy().astype(np.float32))
+    arrays = {"theta": theta.detach().cpu().numpy().astype(np.float32)}
+    if env is not None:
+        arrays.update(env_geo=np.array([env["k"], env["g"], env["log2_pool"], env["width"]], dtype=np.uint32),
+                      env_lo=np.asarray(env["lo"], dtype=np.float32), env_hi=np.asarray(env["hi"], dtype=np.float32))
+    np.savez(path, **arrays)
     with open(path.replace(".npz", ".json"), "w") as f:
         json.dump(meta, f, indent=1)
 
@@ -189,6 +226,15 @@ def load(path: str = WEIGHTS, device="cuda") -> torch.Tensor:
         return torch.from_numpy(z["theta"].astype(np.float32)).to(device)
 
 
+def load_envelope(path: str = WEIGHTS) -> dict | None:
+    """The training envelope stored with the weights, or None."""
+    with np.load(path, allow_pickle=False) as z:
+        if "env_geo" not in z:
+            return None
+        k, g, c, w = (int(v) for v in z["env_geo"])
+        return {"k": k, "g": g, "log2_pool": c, "width": w, "lo": z["env_lo"].copy(), "hi": z["env_hi"].copy()}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--states", type=int, default=20_000_000)
@@ -196,11 +242,28 @@ def main() -> int:
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--lr", type=float, default=3e-3)
     ap.add_argument("--out", default=WEIGHTS)
+    ap.add_argument("--envelope-only", type=int, default=0, metavar="EPISODES",
+                    help="keep the trained weights in --out and store with them the envelope measured on "
+                         "the first EPISODES training episodes (regenerated)")
     args = ap.parse_args()
     dev = torch.device("cuda")
     t0 = time.time()
-    bg = background(16, dev)
+    bg = background(BG_SLICES, dev)
     log(f"[train] background ready {time.time() - t0:.1f}s")
+    if args.envelope_only:
+        theta = load(args.out, dev)
+        with open(args.out.replace(".npz", ".json")) as f:
+            meta = json.load(f)
+        parts = []
+        for s0 in range(1000, 1000 + args.envelope_only, 8):
+            parts.append(generate(range(s0, min(s0 + 8, 1000 + args.envelope_only)), bg, device=dev))
+            log(f"[train] envelope: {s0 + 8 - 1000} episodes {time.time() - t0:.1f}s")
+        data = StateSet(*(torch.cat([getattr(p, f) for p in parts]) for f in ("x", "r", "y", "cf", "truth")))
+        meta["envelope"] = {"episodes": args.envelope_only, "states": len(data),
+                            "note": "feature ranges of the first training episodes (seeds 1000+), regenerated"}
+        save(theta, args.out, meta, envelope_of(data))
+        print(json.dumps(meta["envelope"]), flush=True)
+        return 0
     parts, have, seed = [], 0, 1000
     while have < args.states:
         chunk = generate(range(seed, seed + 8), bg, device=dev)
@@ -221,7 +284,7 @@ def main() -> int:
             "batch": args.batch, "lr": args.lr, "loss_history": hist,
             "held_out_seeds": HELD_OUT_SEEDS, "held_out": res, "train_subset": res_train,
             "seconds": time.time() - t0}
-    save(theta, args.out, meta)
+    save(theta, args.out, meta, envelope_of(data))
     print(json.dumps(meta["held_out"]), flush=True)
     return 0
 

@@ -1,6 +1,8 @@
 """Batched sketches (one persistent launch per phase, hipGraph replay,
-autotuned launch shapes): every member sketch bit-exact with the oracle and
-with the same sketch driven alone through the single-sketch calls."""
+autotuned launch shapes): every member sketch bit-exact with its oracle twin
+(eager, under graph replay, after the autotuner and under two hand-set
+launch shapes) and with the same sketch driven alone through the
+single-sketch calls."""
 import time
 
 import numpy as np
@@ -70,9 +72,26 @@ def _members_small():
     return ms
 
 
-def _run_pair(members, n_slices, counts_fn, graph=True, tune_at=None, check_every=1):
+def _check_oracle(sk, est, live, ref, hosts_np, idx, what):
+    """A batch member against its oracle twin: pool bytes, clock and census
+    bit-exact; live counts exact and estimates within the bar on hosts idx."""
+    pool, t, bact0, closed = sk.read_state()
+    assert (t, bact0, closed) == (ref.t, ref.bact0, True), what
+    assert np.array_equal(pool, ref.packed_pool()), what
+    assert np.array_equal(sk.census(), ref.census()), what
+    r_est, r_live, _ = ref.estimate(hosts_np[idx])
+    assert np.array_equal(_u32(live)[idx], r_live), what
+    e = est.cpu().numpy().astype(np.float64)[idx]
+    assert np.all(np.abs(e - r_est) <= _tol(r_est, ref.g)), what
+
+
+def _run_pair(members, n_slices, counts_fn, graph=True, tune_at=None, check_every=1, oracle=True,
+              oracle_hosts=None, oracle_every=1, tunes=None):
     """Drive the members through a batch (eager first slice, then graph
-    replays) and the same configs through standalone sketches; compare."""
+    replays) and the same configs through standalone sketches and through
+    oracle twins (Alg. 4's per-slice loop on the CPU); compare.  oracle_hosts
+    caps the hosts per member whose estimates the oracle recomputes (a seeded
+    sample); tunes maps a slice to launch shapes set before it."""
     dev = torch.device("cuda")
     cfgs = [Config(m.log2_pool, m.width, m.k, m.g, 0, m.seed, m.seed + 1) for m in members]
     hosts = []
@@ -86,12 +105,22 @@ def _run_pair(members, n_slices, counts_fn, graph=True, tune_at=None, check_ever
     A = [Sketch(c) for c in cfgs]
     B = [Sketch(c) for c in cfgs]
     batch = Batch(A, caps, hosts)
+    O = [OracleSketch(c.log2_pool, c.width, c.k, c.g, c.seed_a, c.seed_b, c.partition) for c in cfgs] \
+        if oracle else []
+    hosts_np = [h.cpu().numpy().view(np.uint32) for h in hosts]
+    pick = np.random.default_rng(17)
+    idx = [np.arange(h.size) if oracle_hosts is None or h.size <= oracle_hosts
+           else np.sort(pick.choice(h.size, oracle_hosts, replace=False)) for h in hosts_np]
     timing = {"eager": [], "replay": []}
     report = None
     for s in range(n_slices):
         slices = [streams.member_slice_torch(m, hosts[i], s, int(counts[s][i]), dev)
                   for i, m in enumerate(members)]
         torch.cuda.synchronize()
+        if tunes and s in tunes:
+            batch.set_tune(tunes[s])
+            if graph and s > 0:
+                batch.capture()      # the graph holds the launch shapes it was captured with
         batch.load(slices)
         batch.synchronize()
         t0 = time.perf_counter()
@@ -120,6 +149,14 @@ def _run_pair(members, n_slices, counts_fn, graph=True, tune_at=None, check_ever
             sk.close_slice()
             refs.append(sk.estimate(hosts[i]))
         torch.cuda.synchronize()
+        for i, ref in enumerate(O):
+            ref.ingest(slices[i].cpu().numpy().view(np.uint32))
+            ref.close_slice()
+        if O and (s % oracle_every == 0 or s == n_slices - 1):
+            batch.synchronize()
+            for i, ref in enumerate(O):
+                _check_oracle(A[i], batch.est[i], batch.live[i], ref, hosts_np[i], idx[i],
+                              f"slice {s} member {i} ({'replay' if kind == 'replay' else 'eager'})")
         if s % check_every == 0 or s == n_slices - 1:
             for i in range(len(members)):
                 pa, ta, ba, ca = A[i].read_state()
@@ -132,6 +169,9 @@ def _run_pair(members, n_slices, counts_fn, graph=True, tune_at=None, check_ever
 
 
 def test_batch_graph_replay_equals_standalone():
+    """Graph replays: every member, after every slice, bit-exact with its
+    oracle twin (pool, clock, census, live counts; estimates within the bar)
+    and identical to its standalone GPU twin."""
     members = _members_small()
     counts = lambda s: streams.batch_packet_counts(4, len(members), s, lo=3.0, hi=5.0)
     timing, _ = _run_pair(members, 12, counts, graph=True)
@@ -139,17 +179,34 @@ def test_batch_graph_replay_equals_standalone():
 
 
 def test_batch_autotune_keeps_results():
+    """The autotuner leaves the slice's results unchanged, and the replays
+    after it match the oracle twins slice by slice."""
     members = _members_small()[:8]
     counts = lambda s: streams.batch_packet_counts(5, len(members), s, lo=3.0, hi=5.0)
     _, report = _run_pair(members, 5, counts, graph=True, tune_at=1)
     assert "best" in report and report["tune"]["estimate_block"] in (64, 128, 256)
 
 
+def test_batch_two_tunings_match_oracle():
+    """The same members under two hand-set launch shapes (small tiles and grids,
+    then large ones), replayed from graphs captured under each: every slice
+    matches the oracle twins."""
+    members = _members_small()[:10]
+    counts = lambda s: streams.batch_packet_counts(6, len(members), s, lo=3.0, hi=5.0)
+    small = {"ingest_tile": 512, "census_tile": 256, "estimate_block": 64, "grid_preserve": 7,
+             "grid_ingest": 13, "grid_census": 11, "grid_estimate": 9}
+    large = {"ingest_tile": 32768, "census_tile": 16384, "estimate_block": 256, "grid_preserve": 512,
+             "grid_ingest": 4096, "grid_census": 2048, "grid_estimate": 8192}
+    _run_pair(members, 8, counts, graph=True, tunes={0: small, 4: large})
+
+
 def test_batch_full_size_16_sketches():
     """16 sketches, pools 2^20..2^26, 1e5..1e7 packets per sketch per slice,
     g = 1024: eager first slice, autotune, captured graph replays; each member
-    bit-exact with its standalone twin at every slice."""
+    bit-exact with its standalone twin at every slice, and with its oracle
+    twin (pool, census; live counts and estimates of 512 sampled hosts) at the
+    eager slice, after the autotuner and at the last replay."""
     members = streams.batch_members(seed=4)
     counts = lambda s: streams.batch_packet_counts(4, len(members), s)
-    timing, report = _run_pair(members, 5, counts, graph=True, tune_at=1)
+    timing, report = _run_pair(members, 5, counts, graph=True, tune_at=1, oracle_hosts=512, oracle_every=2)
     print("batch timing (s)", timing, "tune", report["tune"] if report else None)

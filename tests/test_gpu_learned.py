@@ -177,3 +177,114 @@ def test_zero_output_layer_gives_closed_form():
     torch.cuda.synchronize()
     cf = e_cf.cpu().numpy()
     np.testing.assert_allclose(e_learn.cpu().numpy(), np.maximum(cf, 1.0), rtol=2e-6)
+
+
+# ------------------------------------------------------------------------------
+# The trained network at the geometry the benchmark runs (k = 60, g = 1024),
+# host by host against the FP64 oracle, and the training envelope.
+
+def _trained_params():
+    from paper_1812_00282_amd import train as T
+    th = np.load(T.WEIGHTS, allow_pickle=False)["theta"].astype(np.float64)
+    d = L.params_from(th)
+    return M.Params(d["W1"], d["b1"], d["W2"], d["b2"], d["w3"], float(d["b3"]))
+
+
+def _k60_sketch(log2_pool=21, n_hosts=3000, slices=64, seed=60):
+    """k = 60, g = 1024 sketch and its oracle twin after `slices` slices of a
+    heavy-tailed stream (per-host universes of 1..3000 opposite hosts)."""
+    rng = np.random.default_rng(seed)
+    cfg = Config(log2_pool, 8, 60, 1024, seed_a=0xA5A5, seed_b=0x5A5A)
+    gpu = Sketch(cfg)
+    ref = OracleSketch(log2_pool, 8, 60, 1024, 0xA5A5, 0x5A5A)
+    hosts = rng.choice(2**32, size=n_hosts, replace=False).astype(np.uint32)
+    card = np.minimum(np.floor(rng.pareto(1.1, n_hosts) + 1), 3000).astype(np.int64)
+    w = card / card.sum()
+    for t in range(slices):
+        h = rng.choice(n_hosts, size=20_000, p=w)
+        j = rng.integers(0, card[h]).astype(np.uint64)
+        bip = (hosts[h].astype(np.uint64) * np.uint64(0x9E37) + j * np.uint64(0x85EBCA6B)) % np.uint64(2**32)
+        pairs = np.stack([hosts[h], bip.astype(np.uint32)], 1)
+        gpu.ingest(pairs)
+        ref.ingest(pairs)
+        gpu.close_slice()
+        ref.close_slice()
+    return cfg, gpu, ref, hosts
+
+
+def test_trained_network_per_host_at_k60():
+    """The committed network on a k = 60, g = 1024 sketch after more than k
+    slices: features built by the FP64 oracle from its own histograms, its
+    forward pass with the GPU's BF16 rounding points, and, per host,
+    |ln(learned estimate) - o_ref| <= 2e-2 on the fused and the partitioned
+    paths (an activation rounded to the other BF16 neighbour moves o by at
+    most |w3_i| 2^-8 |a2_i|); the closed-form outputs within 1e-6 of Eq. 11."""
+    cfg, gpu, ref, hosts = _k60_sketch()
+    r_est, r_live, r_hist = ref.estimate(hosts, want_hist=True)
+    occ = (ref.N - ref.pool_inactive(cfg.k)) / ref.N
+    r_o = np.log(np.maximum(r_est, 1.0))
+    xo = M.features(r_hist, r_live, cfg.g, cfg.k, occ, r_o)
+    o_ref, _ = M.forward(_trained_params(), xo, r_o)
+    from paper_1812_00282_amd import train as T
+    w = L.pack(T.load(), L.new_weights())
+    tol_cf = 1e-6 * np.abs(r_est) + cfg.g * 64 * 2.0**-52
+    for part in (False, True):
+        learn, cf = L.estimate_learned(gpu, hosts, w, partitioned=part)
+        torch.cuda.synchronize()
+        cfv = cf.cpu().numpy().astype(np.float64)
+        assert np.all(np.abs(cfv - r_est) <= tol_cf), part
+        lo = np.log(learn.cpu().numpy().astype(np.float64))
+        err = np.abs(lo - o_ref)
+        assert np.all(err <= 2e-2), (part, float(err.max()), int(np.argmax(err)))
+        assert float(err.mean()) < 2e-3, part
+    assert L.fallbacks(w) == 0       # no envelope set: the network runs for every host
+
+
+def test_envelope_other_geometry_gives_closed_form():
+    """Weights whose envelope names another geometry (k = 60, 2^28 x 8-bit,
+    g = 1024) on a k = 4 sketch: every learned estimate is exactly the closed
+    form, on both paths, and every host is counted."""
+    from paper_1812_00282_amd import train as T
+    wl, pop, gpu, ref = _small_sketch()
+    env = {"k": 60, "g": 1024, "log2_pool": 28, "width": 8,
+           "lo": np.full(64, -1e30, np.float32), "hi": np.full(64, 1e30, np.float32)}
+    w = L.set_envelope(L.pack(T.load(), L.new_weights()), env)
+    hosts = pop.aips
+    for part in (False, True):
+        learn, cf = L.estimate_learned(gpu, hosts, w, partitioned=part)
+        torch.cuda.synchronize()
+        assert torch.equal(learn, cf), part
+        assert L.fallbacks(w, reset=True) == hosts.size, part
+    r_est, _, _ = ref.estimate(hosts)
+    assert np.all(np.abs(cf.cpu().numpy() - r_est) <= 1e-6 * np.abs(r_est) + wl.g * 64 * 2.0**-52)
+
+
+def test_envelope_per_host_ranges():
+    """An envelope with the sketch's own geometry whose live-fraction range
+    stops at the median: hosts above it get exactly the closed form, the
+    others exactly the network's estimate without an envelope; the counter
+    holds the number of hosts above it.  Both paths."""
+    from paper_1812_00282_amd import train as T
+    cfg, gpu, ref, hosts = _k60_sketch(log2_pool=20, n_hosts=2000, slices=62, seed=61)
+    _, live, _ = gpu.estimate(hosts)
+    torch.cuda.synchronize()
+    xl = M.bf16_round(live.cpu().numpy().astype(np.float64) / cfg.g)   # feature k as the network reads it
+    hi_live = float(np.median(xl))
+    lo = np.full(64, -1e30, np.float32)
+    hi = np.full(64, 1e30, np.float32)
+    hi[cfg.k] = hi_live
+    outside = xl > hi_live
+    assert 0 < outside.sum() < hosts.size
+    env = {"k": cfg.k, "g": cfg.g, "log2_pool": cfg.log2_pool, "width": cfg.width, "lo": lo, "hi": hi}
+    theta = T.load()
+    plain = L.pack(theta, L.new_weights())
+    guarded = L.set_envelope(L.pack(theta, L.new_weights()), env)
+    for part in (False, True):
+        free, cf = L.estimate_learned(gpu, hosts, plain, partitioned=part)
+        got, cf2 = L.estimate_learned(gpu, hosts, guarded, partitioned=part)
+        torch.cuda.synchronize()
+        assert torch.equal(cf, cf2)
+        out = torch.from_numpy(outside).cuda()
+        assert torch.equal(got[out], cf[out]), part
+        assert torch.equal(got[~out], free[~out]), part
+        assert L.fallbacks(guarded, reset=True) == int(outside.sum()), part

@@ -311,25 +311,29 @@ def test_estimate_precision_near_cancellation():
 @pytest.mark.parametrize("k,w,c", streams.SWEEP)
 def test_window_width_sweep(k, w, c):
     """Window/width sweep on the small stream for 3k+8 slices (every block's
-    ACT wraps): pool bit-exact at checkpoints through the run, estimates and
-    live counts of all 1000 hosts (k' = k and k' = k/2) at the last slice."""
+    ACT wraps): the full pool and clock bit-exact after every slice for
+    k <= 64 and every k slices for k = 256; live counts, histograms and
+    estimates of all 1000 hosts (k' = k and k' = k/2) at four points of the
+    run."""
     wl = streams.sweep_workload(k, w, c)
     pop = wl.population()
     cfg = Config(c, w, k, wl.g, seed_a=k, seed_b=c)
     gpu, ref = _pair(cfg)
     n_slices = wl.n_slices
-    checkpoints = {n_slices // 3, (2 * n_slices) // 3, n_slices - 1}
+    state_every = 1 if k <= 64 else k
+    est_points = {n_slices // 4, n_slices // 2, (3 * n_slices) // 4, n_slices - 1}
     for t in range(n_slices):
         pairs = wl.slice(pop, t)
         gpu.ingest(pairs)
         ref.ingest(pairs)
         gpu.close_slice()
         ref.close_slice()
-        if t in checkpoints:
+        if t % state_every == 0 or t == n_slices - 1:
             _check_state(gpu, ref, f"k={k} slice {t}")
-    for kp in sorted({k, max(1, k // 2)}):
-        _check_estimates(gpu, ref, pop.aips, kprime=kp, hist=(kp == k and k <= 256),
-                         what=f"k={k} k'={kp}")
+        if t in est_points:
+            for kp in sorted({k, max(1, k // 2)}):
+                _check_estimates(gpu, ref, pop.aips, kprime=kp, hist=(kp == k and k <= 256),
+                                 what=f"k={k} slice {t} k'={kp}")
 
 
 # ------------------------------------------------------------ full size --

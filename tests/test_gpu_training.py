@@ -33,7 +33,7 @@ def test_probe_truth_matches_hash_sets():
 
 @pytest.fixture(scope="module")
 def bg():
-    return T.background(4, torch.device("cuda"))
+    return T.background(T.BG_SLICES, torch.device("cuda"))
 
 
 def test_training_beats_closed_form_on_held_out(bg):
