@@ -466,11 +466,12 @@ def main() -> int:
                 "avg_launch_ms": est_ms,
                 "traffic_gbs": traffic / (est_ms * 1e-3) / 1e9 if traffic else None,
                 "traffic_frac": traffic / (est_ms * 1e-3) / 1e9 / HBM_PEAK_GBS if traffic else None,
-                "random_lines_per_s": wl.g * pop.n_hosts / (est_ms * 1e-3),
-                # VAT lookups per second against the rate at which HBM could
-                # serve one random 64-byte sector per lookup (peak / 64 B):
-                # above 1 means the lookups beat a random-gather design.
-                "random_lines_vs_sector_bound": wl.g * pop.n_hosts / (est_ms * 1e-3)
+                "lookups_per_s": wl.g * pop.n_hosts / (est_ms * 1e-3),
+                # VAT lookups per second against the rate a random-gather
+                # design could reach if HBM served one 64-byte sector per
+                # lookup at peak (context for the lookup design; the roofline
+                # figure is frac, and traffic_frac for the bytes moved)
+                "lookups_vs_random_gather_bound": wl.g * pop.n_hosts / (est_ms * 1e-3)
                 / (HBM_PEAK_GBS * 1e9 / 64)}
 
     line = {

@@ -7,9 +7,9 @@
   CheckAT must agree with it exactly for every k' <= k, which makes it an
   independent check of the oracle's AT state machine (ACT clock, blocks,
   preservation schedule and Algorithm 3).
-* ``le_std_error``: standard error of the linear-counting estimate
-  (Whang et al., cited in Sec. 2.1); ``virtual_std_error`` the same delta
-  method for the pool-shared (virtual) estimator.  Used as accuracy bounds.
+* ``virtual_std_error``: the delta-method standard error of the pool-shared
+  (virtual) estimator, after linear counting's (Whang et al., cited in
+  Sec. 2.1).  Used as an accuracy bound.
 """
 from __future__ import annotations
 
@@ -57,11 +57,3 @@ def virtual_std_error(n: float, g: int, zp: float) -> float:
     q = zp * math.exp(-n / g)
     return math.sqrt(g * (1.0 - q) / q) / n
 
-
-def le_std_error(n: float, g: int) -> float:
-    """Standard error of linear counting with g bits and n items
-    (Whang, Vander-Zanden, Taylor 1990): sqrt(g (e^t - t - 1)) / n, t = n/g."""
-    if n <= 0:
-        return 0.0
-    t = n / g
-    return math.sqrt(g * (math.exp(t) - t - 1.0)) / n

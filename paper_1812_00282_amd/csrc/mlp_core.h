@@ -63,13 +63,22 @@ __device__ __forceinline__ bool env_geometry_off(const Packed *P, uint32_t k, ui
     return env_on(P) && (P->env.k != k || P->env.g != g || P->env.log2_pool != c || P->env.width != w);
 }
 
-// Whether feature f with BF16 bits xb lies outside the envelope (false
-// without one).
-__device__ __forceinline__ bool env_outside(const Packed *P, int f, uint16_t xb)
+// The range of feature f ([-inf, inf] without an envelope), read once per
+// lane, and whether a feature's BF16 bits xb lie outside it.
+struct EnvRange {
+    float lo, hi;
+};
+
+__device__ __forceinline__ EnvRange env_range(const Packed *P, int f)
 {
-    if (!env_on(P)) return false;
+    if (!env_on(P)) return {-INFINITY, INFINITY};
+    return {P->env.lo[f], P->env.hi[f]};
+}
+
+__device__ __forceinline__ bool env_outside(const EnvRange &r, uint16_t xb)
+{
     const float x = __uint_as_float((uint32_t)xb << 16);
-    return !(x >= P->env.lo[f] && x <= P->env.hi[f]);
+    return !(x >= r.lo && x <= r.hi);
 }
 
 // Adds n hosts to the envelope's fallback count (one lane per call).

@@ -324,6 +324,46 @@ __device__ __forceinline__ uint32_t census_chunk(const Geo &G, const uint4 &v, u
     return bits;
 }
 
+// Byte ATs of a chunk inside one block: the activity test four ATs at a time
+// in packed 16-bit lanes (each 32-bit word split into its even and odd
+// bytes).  For ACT a and value v in [0, 2k]: u = a + 2k - v, the distance is
+// (a - v) mod 2k = min(u, u - 2k) (the second wraps when u < 2k), raised to
+// at least k when v = 2k (inactive), and the AT is active iff it is below k.
+// A DR's value is its distance.  Only the active ATs (a few per cent) take
+// the per-AT histogram step.
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint32_t active_bits8(const Geo &G, const uint4 &v, uint32_t act)
+{
+    const u16x2 K = (u16x2)(unsigned short)G.k;
+    const u16x2 A = (u16x2)(unsigned short)(act + G.twok);
+    const u16x2 T = (u16x2)(unsigned short)G.twok;
+    const u16x2 T1 = (u16x2)(unsigned short)(G.twok - 1u);
+    const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+    uint32_t bits = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        uint32_t f2[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const u16x2 x = __builtin_bit_cast(u16x2, (w4[j] >> (8 * h)) & 0x00FF00FFu);
+            u16x2 d;
+            if (G.dr) {
+                d = x;
+            } else {
+                const u16x2 u = A - x;
+                d = __builtin_elementwise_min(u, u - T);
+                d = __builtin_elementwise_max(d, __builtin_elementwise_sub_sat(x, T1) * K);
+            }
+            f2[h] = __builtin_bit_cast(uint32_t, (u16x2)((d - K) >> (unsigned short)15));   // 1 iff d < k
+        }
+        // f2[0] holds bytes 0 and 2 of word j, f2[1] bytes 1 and 3
+        const uint32_t x = f2[0] | (f2[1] << 1);
+        bits |= ((x & 3u) | ((x >> 14) & 0xCu)) << (4 * j);
+    }
+    return bits;
+}
+
 template <int W>
 __global__ void __launch_bounds__(256) k_census(Geo G, const uint4 *__restrict__ pool4, uint64_t nchunks,
                                                 DevState *__restrict__ st, uint8_t *__restrict__ bitmap)
@@ -348,6 +388,28 @@ __global__ void __launch_bounds__(256) k_census(Geo G, const uint4 *__restrict__
         for (int u = 0; u < U; ++u) {
             const uint64_t ch = c0 + u * stride;
             if (ch >= nchunks) continue;
+            if constexpr (W == 8) {
+                // a chunk inside one block (or any chunk of DRs) takes the packed test
+                const uint32_t p0 = (uint32_t)(ch * 16u);
+                uint32_t bid0 = 0, act = 0;
+                bool one = G.dr != 0;
+                if (!one && G.fast_blocks) {
+                    bid0 = block_of(G, p0);
+                    one = (uint64_t)p0 + 16u <= block_start(G, bid0 + 1);
+                    act = block_act(G, bact0, bid0);
+                }
+                if (one && lds) {
+                    uint32_t bits = active_bits8(G, v[u], act);
+                    store_bits<8>(bitmap, ch, bits);
+                    while (bits) {
+                        const uint32_t e = __builtin_ctz(bits);
+                        bits &= bits - 1u;
+                        const uint32_t val = chunk_get<8>(v[u], e);
+                        atomicAdd(&hist[G.dr ? val : at_dist(G, act, val)], 1u);
+                    }
+                    continue;
+                }
+            }
             store_bits<W>(bitmap, ch, census_chunk<W>(G, v[u], ch, bact0, lds ? hist : nullptr, census_of(st)));
         }
     }
@@ -570,6 +632,7 @@ __global__ void __launch_bounds__(256) k_estimate_learned(Geo G, const uint8_t *
     uint16_t *xs = xs_all[wave];
     __syncthreads();
     const bool geo_off = mlp::env_geometry_off(P, G.k, G.g, G.c, G.wb);
+    const mlp::EnvRange rng = mlp::env_range(P, (int)lane);   // this lane's feature in every row
     for (int t = 0; t < 4; ++t) {
         // features of hosts 16t .. 16t+15 of this wavefront (row m = host - 16t);
         // lane f builds feature f of a row, so one ballot per row says whether
@@ -588,7 +651,7 @@ __global__ void __launch_bounds__(256) k_estimate_learned(Geo G, const uint8_t *
                 x = logf(fmaxf(cf_all[wave][host], 1.0f)) * 0.0625f;
             const uint16_t xb = mlp::bf16_bits(x);
             xs[m * mlp::LDS_STRIDE + f] = xb;
-            if (__ballot(mlp::env_outside(P, f, xb))) outside |= 1u << m;
+            if (__ballot(mlp::env_outside(rng, xb))) outside |= 1u << m;
         }
         __syncthreads();
         float r4[4];

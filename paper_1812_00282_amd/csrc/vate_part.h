@@ -488,6 +488,7 @@ __device__ __forceinline__ void learned16(const Geo &G, float occupancy, const u
     // Row m (host m) is built by the whole wavefront, lane f = feature f, so
     // one ballot per row says whether the host is outside the envelope.
     uint32_t outside = mlp::env_geometry_off(P, G.k, G.g, G.c, G.wb) ? 0xFFFFu : 0u;
+    const mlp::EnvRange rng = mlp::env_range(P, l);     // this lane's feature in every row
     for (int e = l; e < 16 * VATE_MLP_FEATURES; e += 64) {
         const int m = e >> 6, f = e & 63;
         float x = 0.f;
@@ -503,7 +504,7 @@ __device__ __forceinline__ void learned16(const Geo &G, float occupancy, const u
         }
         const uint16_t xb = mlp::bf16_bits(x);
         xs[m * mlp::LDS_STRIDE + f] = xb;
-        if (__ballot(mlp::env_outside(P, f, xb))) outside |= 1u << m;
+        if (__ballot(mlp::env_outside(rng, xb))) outside |= 1u << m;
     }
     __syncthreads();
     float r4[4];
