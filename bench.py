@@ -38,12 +38,17 @@ def log(msg: str) -> None:
 
 
 def kernel_source_hash() -> str:
-    """Hash of the sources that define the estimate-phase kernels."""
+    """Hash of the code (comments and whitespace left out) of the sources that
+    define the estimate-phase kernels."""
     import hashlib
+    import re
 
+    tok = re.compile(r'"(?:\\.|[^"\\\n])*"|\'(?:\\.|[^\'\\\n])*\'|//[^\n]*|/\*.*?\*/|[^\s"\'/]+|\S', re.S)
     h = hashlib.sha256()
     for f in ("vate.hip", "vate_core.h", "vate_part.h", "vate_exact.h", "mlp_core.h"):
-        h.update(open(os.path.join(ROOT, "paper_1812_00282_amd", "csrc", f), "rb").read())
+        text = open(os.path.join(ROOT, "paper_1812_00282_amd", "csrc", f)).read()
+        code = [t for t in tok.findall(text) if not t.startswith(("//", "/*"))]
+        h.update(" ".join(code).encode())
     return h.hexdigest()[:16]
 
 

@@ -9,34 +9,35 @@
 // for the window k) fill 128 KiB of LDS:
 //
 //  k_run_scatter  persistent workgroups, one subgroup of hosts at a time.
-//                 Hashes the subgroup's VATs (their slices stay in
-//                 registers), counts them per slice in LDS, places their
-//                 16-bit indices by an LDS counting sort (two bytes a slot is
-//                 what lets a subgroup hold 63 hosts of g = 1024), then
-//                 copies the sorted entries (host within subgroup, AT within
-//                 slice; the pid hashed again from the index) to the
+//                 Hashes the subgroup's VATs once (each pid stays in a
+//                 register, 40 per thread), counts them per slice in LDS and
+//                 places 32-bit entries (host within subgroup, AT within
+//                 slice) by an LDS counting sort, then copies them to the
 //                 workspace as one coalesced stream.  Every (subgroup, slice)
-//                 run starts on a 4-entry boundary (padded with kRunPad), so
-//                 no 16-byte chunk is shared by two runs.  Run starts, in
-//                 chunks, go to the subgroup's row of the run table.
-//  k_run_lookup   one slice's bits in LDS per workgroup (each slice's walk
-//                 over the subgroups split over a few workgroups on one XCD).
-//                 A wavefront takes the runs of eight subgroups as one flat
-//                 list of chunks, tests every entry's bit, and only for the
-//                 live ones (active for window k: a few per cent of the VATs
-//                 in steady state) reads the AT from the pool for its
-//                 distance (Eq. 5).  The live results - host within subgroup
-//                 and distance in 16 bits - are packed to the front of the
-//                 run's own result slots, ranked by ballot and popcount, and
-//                 the run's live count goes beside its start in the table.
-//  k_run_finalize one workgroup per subgroup.  Reads the live results of
-//                 its runs, builds each host's distance histogram in LDS (the
-//                 inactive bin k is g minus the rest) and forms Eq. 11 for
+//                 run starts on a 4-entry boundary (padded with the slice's
+//                 sentinel entry), so no 16-byte chunk is shared by two runs.
+//                 Run starts, in chunks, go to the subgroup's row of the run
+//                 table.
+//  k_run_lookup   one slice's bits in LDS per workgroup (a slice's walk over
+//                 the subgroups may be split over a few workgroups; the
+//                 slices of one XCD are contiguous).  Where they fit, the
+//                 distances (Eq. 5) of the slice's live ATs are computed once
+//                 into LDS in slice order, indexed by the AT's rank among the
+//                 live bits.  A wavefront takes the runs of 64 subgroups as one
+//                 flat list of chunks and tests every entry's bit; only the
+//                 live ones (active for window k: about 1 % of the VATs in the
+//                 40 Gb/s steady state) take a slot of their run from an LDS
+//                 counter and write (host within subgroup, distance) there,
+//                 in the entries' own positions of the result array.  The
+//                 run's live count goes beside its start in the table.
+//  k_run_finalize a few subgroups per workgroup.  Reads the live results of
+//                 their runs, builds each host's distance histogram in LDS
+//                 (the inactive bin k is g minus the rest) and forms Eq. 11 for
 //                 k', several windows, or the learned estimate (the network
 //                 fed from the LDS histograms, 16 hosts per wavefront).
 //
 // HBM traffic per VAT: the 4-byte entry written and read back once; per live
-// VAT a pool read and 2 bytes written and read back.
+// VAT 4 bytes of result written and read back.
 
 constexpr uint32_t kRunThreads = 1024;                          // scatter / lookup workgroup
 constexpr uint32_t kRunPerThread = 40;                          // VATs hashed per scatter thread (pids held in registers)

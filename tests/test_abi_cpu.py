@@ -170,3 +170,23 @@ def test_host_block_matches_oracle(c, k, partition):
             ap, bp = N // twok, N % twok
             want = pid // ap if pid < ap * (twok - bp) else (pid + twok - bp) // (ap + 1)
         assert got == want, (pid, got, want)
+
+
+def test_kernel_source_hash_ignores_comments(tmp_path, monkeypatch):
+    """The hash that ties a committed traffic summary to the kernel sources
+    changes with the code and not with its comments or spacing."""
+    import shutil
+
+    import bench
+
+    src = os.path.join(bench.ROOT, "paper_1812_00282_amd", "csrc")
+    dst = tmp_path / "paper_1812_00282_amd" / "csrc"
+    shutil.copytree(src, dst)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    h0 = bench.kernel_source_hash()
+    f = dst / "vate_part.h"
+    text = f.read_text()
+    f.write_text("// another comment\n" + text.replace("\n", "\n\n", 3) + "/* trailing */\n")
+    assert bench.kernel_source_hash() == h0
+    f.write_text(text.replace("kLookU = 8", "kLookU = 4", 1))
+    assert bench.kernel_source_hash() != h0
