@@ -209,7 +209,7 @@ def generate_slices(wl, pop, n: int) -> list:
         return list(ex.map(lambda s: wl.slice(pop, s), range(n)))
 
 
-def batched_leg(dev, n_slices: int = 8) -> dict:
+def batched_leg(dev, n_slices: int = 8, tune_cache: str | None = None) -> dict:
     """16 independent sketches (pools 2^20..2^26, k in {8..128}, g = 1024,
     1e5..1e7 packets per sketch per slice) advanced a slice at a time by the
     batched launches: the first slice eager, then the autotuner, a captured
@@ -247,7 +247,11 @@ def batched_leg(dev, n_slices: int = 8) -> dict:
         batch.synchronize()
         times.append(time.perf_counter() - t0)
         if s == 0:
-            tune = batch.autotune()["tune"]
+            t0 = time.perf_counter()
+            rep = batch.autotune(cache=tune_cache)
+            tune = dict(rep["tune"], cached=rep["cached"], key=batch.geometry_key(), cache=tune_cache,
+                        seconds=time.perf_counter() - t0,
+                        candidates=len(rep.get("candidates", [])))
             batch.capture()
     solo = [Sketch(c, device=dev) for c in cfgs]
     seq = []
@@ -326,6 +330,10 @@ def main() -> int:
                     help="skip the batched-sketches leg (16 sketches, hipGraph replay)")
     ap.add_argument("--no-blocked", action="store_true",
                     help="skip the locality-blocked H leg (opt-in variant, not the paper's H)")
+    ap.add_argument("--tune-cache", default=os.environ.get(
+                        "VATE_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "vate", "batch_tune.json")),
+                    help="JSON file of autotuned batch launch shapes, keyed by the batch geometry "
+                         "('' to autotune every run without a cache)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device-to-device copy (reference kernel for "
                          "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE readings)")
@@ -526,7 +534,7 @@ def main() -> int:
         log("[bench] batched sketches")
         del sk
         torch.cuda.empty_cache()
-        line["batched"] = batched_leg(dev)
+        line["batched"] = batched_leg(dev, tune_cache=args.tune_cache or None)
     if cpu is not None:
         line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)

@@ -32,8 +32,11 @@ typedef struct vate_batch vate_batch;
 typedef struct vate_batch_tune {
     uint32_t ingest_tile;     /* packets per claimed tile, multiple of 512 */
     uint32_t census_tile;     /* 16-byte pool chunks per tile, multiple of 256 */
-    uint32_t estimate_block;  /* hosts per tile (64, 128 or 256) */
+    uint32_t estimate_block;  /* threads per estimate workgroup (64, 128 or 256) */
     uint32_t grid_preserve, grid_ingest, grid_census, grid_estimate;  /* workgroups */
+    uint32_t estimate_lanes;  /* lanes sharing one host's g gathers (1, 4 or 16);
+                                 hosts per estimate tile = estimate_block / estimate_lanes */
+    uint32_t census_unroll;   /* pool chunks in flight per census thread (1, 2 or 4) */
 } vate_batch_tune;
 
 /* Device bytes (256-byte aligned block) for a batch of n sketches, n <= 64. */
@@ -72,11 +75,13 @@ int vate_batch_replay(vate_batch *b, void *stream);
 int vate_batch_get_tune(const vate_batch *b, vate_batch_tune *t);
 int vate_batch_set_tune(vate_batch *b, const vate_batch_tune *t);
 
-/* Time candidate tile sizes and grid sizes of the ingest, census and
- * estimate phases on the current slice (every sketch closed) and keep the
- * fastest; outputs stay those of the slice.  report (nullable) receives a
- * JSON text of the candidates and the choice.  Synchronises `stream` and
- * drops any captured graph. */
+/* Time candidate launch shapes of the ingest (tile x grid), census (tile x
+ * chunks in flight per thread x grid) and estimate (workgroup size x lanes
+ * per host x grid) phases on the current slice (every sketch closed) and
+ * keep the fastest per phase; outputs stay those of the slice.  report
+ * (nullable) receives a JSON text of the candidates and the choice (cut at
+ * report_len).  Synchronises `stream` and drops any captured graph.
+ * Errors: VATE_E_INVAL, VATE_E_STATE (a sketch not closed), VATE_E_DEVICE. */
 int vate_batch_autotune(vate_batch *b, void *stream, char *report, size_t report_len);
 
 const char *vate_batch_last_error(const vate_batch *b);

@@ -98,7 +98,7 @@ _SIGS.update({
 class VateBatchTune(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint32) for n in
                 ("ingest_tile", "census_tile", "estimate_block", "grid_preserve",
-                 "grid_ingest", "grid_census", "grid_estimate")]
+                 "grid_ingest", "grid_census", "grid_estimate", "estimate_lanes", "census_unroll")]
 
 
 _SIGS.update({

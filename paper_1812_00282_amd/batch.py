@@ -46,8 +46,9 @@ class Batch:
         _check(lib().vate_batch_create(handles, S, self.block.data_ptr(), self.n_pairs.data_ptr(),
                                        ctypes.byref(h)), None)
         self._h = h
+        self.kprime = [s.cfg.k if kprime is None else kprime[i] for i, s in enumerate(sketches)]
         for i, s in enumerate(sketches):
-            kp = s.cfg.k if kprime is None else kprime[i]
+            kp = self.kprime[i]
             lv = self.live[i]
             _check(lib().vate_batch_set_io(h, i, self.pairs[i].data_ptr(), self.pairs[i].shape[0],
                                            self.hosts[i].data_ptr(),
@@ -92,29 +93,52 @@ class Batch:
         return {n: getattr(t, n) for n, _ in VateBatchTune._fields_}
 
     def set_tune(self, tune: dict) -> None:
-        t = VateBatchTune(**tune)
+        """Set launch shapes; fields missing from `tune` keep their values."""
+        cur = self.get_tune()
+        cur.update(tune)
+        t = VateBatchTune(**cur)
         _check(lib().vate_batch_set_tune(self._h, ctypes.byref(t)), self._h)
 
+    def geometry_key(self) -> str:
+        """What a tuned launch shape depends on: the device (name, CUs) and,
+        per member, pool size, width, window, g, counter kind, hosts, window
+        estimated and pair capacity."""
+        props = torch.cuda.get_device_properties(self.device)
+        parts = [f"{props.name}/{props.multi_processor_count}cu"]
+        for s, h, buf, kp in zip(self.sketches, self.hosts, self.pairs, self.kprime):
+            c = s.cfg
+            parts.append(f"c{c.log2_pool}w{c.width}k{c.k}g{c.g}x{c.counter}b{c.block_log2}"
+                         f"h{h.numel()}kp{kp}p{buf.shape[0]}")
+        return "|".join(parts)
+
     def autotune(self, cache: str | None = None, key: str | None = None) -> dict:
-        """Run the library's autotuner on the current slice (or reuse a cached
-        choice for `key` from the JSON file `cache`) and return the choice."""
-        if cache and key and os.path.exists(cache):
+        """Run the library's autotuner on the current slice and return its
+        report ("candidates", "best", "tune").  With a JSON file `cache`, a
+        choice stored there under `key` (default: geometry_key()) is set
+        instead ({"cached": True, "tune": ...}); a new choice is stored."""
+        if cache and key is None:
+            key = self.geometry_key()
+        if cache and os.path.exists(cache):
             with open(cache) as f:
                 known = json.load(f)
             if key in known:
                 self.set_tune(known[key])
-                return {"cached": True, "best": known[key]}
+                return {"cached": True, "key": key, "tune": self.get_tune()}
         buf = ctypes.create_string_buffer(1 << 16)
         _check(lib().vate_batch_autotune(self._h, self.stream.cuda_stream, buf, len(buf)), self._h)
         rep = json.loads(buf.value.decode())
         rep["tune"] = self.get_tune()
-        if cache and key:
+        rep["cached"] = False
+        if cache:
+            rep["key"] = key
             known = {}
             if os.path.exists(cache):
                 with open(cache) as f:
                     known = json.load(f)
             known[key] = rep["tune"]
             os.makedirs(os.path.dirname(os.path.abspath(cache)), exist_ok=True)
-            with open(cache, "w") as f:
+            tmp = cache + ".tmp"
+            with open(tmp, "w") as f:
                 json.dump(known, f, indent=1)
+            os.replace(tmp, cache)
         return rep

@@ -364,6 +364,41 @@ __device__ __forceinline__ uint32_t active_bits8(const Geo &G, const uint4 &v, u
     return bits;
 }
 
+// One chunk of the census with the fast paths: an all-inactive chunk (most
+// of them in steady state) has no bits; byte ATs of a chunk inside one block
+// (or any chunk of byte DRs) take the packed test when the histogram is in
+// LDS; anything else goes through census_chunk.
+template <int W>
+__device__ __forceinline__ uint32_t census_chunk_fast(const Geo &G, const uint4 &v, uint64_t ch, uint32_t bact0,
+                                                      uint32_t pat, uint32_t *hist, unsigned long long *census)
+{
+    if constexpr (W == 8) {
+        if (v.x == pat && v.y == pat && v.z == pat && v.w == pat) return 0u;
+        if (hist) {
+            const uint32_t p0 = (uint32_t)(ch * 16u);
+            uint32_t bid0 = 0, act = 0;
+            bool one = G.dr != 0;
+            if (!one && G.fast_blocks) {
+                bid0 = block_of(G, p0);
+                one = (uint64_t)p0 + 16u <= block_start(G, bid0 + 1);
+                act = block_act(G, bact0, bid0);
+            }
+            if (one) {
+                const uint32_t bits = active_bits8(G, v, act);
+                uint32_t rest = bits;
+                while (rest) {
+                    const uint32_t e = __builtin_ctz(rest);
+                    rest &= rest - 1u;
+                    const uint32_t val = chunk_get<8>(v, e);
+                    atomicAdd(&hist[G.dr ? val : at_dist(G, act, val)], 1u);
+                }
+                return bits;
+            }
+        }
+    }
+    return census_chunk<W>(G, v, ch, bact0, hist, census);
+}
+
 template <int W>
 __global__ void __launch_bounds__(256) k_census(Geo G, const uint4 *__restrict__ pool4, uint64_t nchunks,
                                                 DevState *__restrict__ st, uint8_t *__restrict__ bitmap)
@@ -387,36 +422,77 @@ __global__ void __launch_bounds__(256) k_census(Geo G, const uint4 *__restrict__
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const uint64_t ch = c0 + u * stride;
-            if (ch >= nchunks) continue;
-            if constexpr (W == 8) {
-                // a chunk inside one block (or any chunk of DRs) takes the packed test
-                const uint32_t p0 = (uint32_t)(ch * 16u);
-                uint32_t bid0 = 0, act = 0;
-                bool one = G.dr != 0;
-                if (!one && G.fast_blocks) {
-                    bid0 = block_of(G, p0);
-                    one = (uint64_t)p0 + 16u <= block_start(G, bid0 + 1);
-                    act = block_act(G, bact0, bid0);
-                }
-                if (one && lds) {
-                    uint32_t bits = active_bits8(G, v[u], act);
-                    store_bits<8>(bitmap, ch, bits);
-                    while (bits) {
-                        const uint32_t e = __builtin_ctz(bits);
-                        bits &= bits - 1u;
-                        const uint32_t val = chunk_get<8>(v[u], e);
-                        atomicAdd(&hist[G.dr ? val : at_dist(G, act, val)], 1u);
-                    }
-                    continue;
-                }
-            }
-            store_bits<W>(bitmap, ch, census_chunk<W>(G, v[u], ch, bact0, lds ? hist : nullptr, census_of(st)));
+            if (ch < nchunks)
+                store_bits<W>(bitmap, ch,
+                              census_chunk_fast<W>(G, v[u], ch, bact0, pat, lds ? hist : nullptr, census_of(st)));
         }
     }
     __syncthreads();
     if (lds)
         for (uint32_t d = threadIdx.x; d < G.k; d += blockDim.x)
             if (hist[d]) atomicAdd(&census_of(st)[d], (unsigned long long)hist[d]);
+}
+
+// k_census8: the census of byte counters with k <= kCensus8Bins.  In steady
+// state only a few per cent of the chunks hold an active AT, but nearly every
+// wavefront has one among its 64, so a per-lane test would run the packed
+// activity test on all of them.  Here each wavefront first writes the zero
+// bits of its all-inactive chunks and stages the others in LDS (compacted,
+// in lane order), then its lanes take the staged chunks one each.
+constexpr uint32_t kCensus8Bins = 256;
+constexpr int kCensus8U = 4;   // chunks per lane and round
+
+__global__ void __launch_bounds__(256) k_census8(Geo G, const uint4 *__restrict__ pool4, uint64_t nchunks,
+                                                 DevState *__restrict__ st, uint8_t *__restrict__ bitmap)
+{
+    constexpr int U = kCensus8U;
+    __shared__ uint32_t hist[kCensus8Bins];
+    __shared__ uint4 stage_v[4][64 * U];
+    __shared__ uint8_t stage_c[4][64 * U];     // u * 64 + lane of the staged chunk
+    for (uint32_t d = threadIdx.x; d < G.k; d += blockDim.x) hist[d] = 0;
+    __syncthreads();
+    const uint32_t bact0 = st->bact0;
+    const uint32_t pat = replicate<8>(inactive_value(G));
+    const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t c0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c0 - lane < nchunks; c0 += U * stride) {
+        uint4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint64_t ch = c0 + u * stride;
+            v[u] = ch < nchunks ? pool4[ch] : make_uint4(pat, pat, pat, pat);
+        }
+        uint32_t n = 0;      // staged chunks of this wavefront (uniform)
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint64_t ch = c0 + u * stride;
+            const bool busy = v[u].x != pat || v[u].y != pat || v[u].z != pat || v[u].w != pat;
+            const uint64_t m = __ballot(busy);
+            if (busy) {
+                const uint32_t pos = n + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+                stage_v[wv][pos] = v[u];
+                stage_c[wv][pos] = (uint8_t)(u * 64 + lane);
+            } else if (ch < nchunks) {
+                store_bits<8>(bitmap, ch, 0u);
+            }
+            n += (uint32_t)__popcll(m);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const uint64_t wbase = c0 - lane;
+        for (uint32_t i = lane; i < n; i += 64) {
+            const uint32_t code = stage_c[wv][i];
+            const uint64_t ch = wbase + (code & 63u) + (uint64_t)(code >> 6) * stride;
+            store_bits<8>(bitmap, ch, census_chunk_fast<8>(G, stage_v[wv][i], ch, bact0, pat, hist, census_of(st)));
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    __syncthreads();
+    for (uint32_t d = threadIdx.x; d < G.k; d += blockDim.x)
+        if (hist[d]) atomicAdd(&census_of(st)[d], (unsigned long long)hist[d]);
 }
 
 // ---------------------------------------------------------------------------
@@ -866,8 +942,12 @@ static void launch_census(vate_sketch *s, hipStream_t st)
                                                              s->st, s->bitmap);
     } else {
         uint64_t nch = s->pool_bytes / 16;
-        k_census<W><<<grid_for(nch, 256 * 4, 2048), 256, 0, st>>>(s->G, reinterpret_cast<const uint4 *>(s->pool),
-                                                                   nch, s->st, s->bitmap);
+        if (W == 8 && s->G.k <= kCensus8Bins)
+            k_census8<<<grid_for(nch, 256 * kCensus8U, 2048), 256, 0, st>>>(
+                s->G, reinterpret_cast<const uint4 *>(s->pool), nch, s->st, s->bitmap);
+        else
+            k_census<W><<<grid_for(nch, 256 * 4, 2048), 256, 0, st>>>(s->G, reinterpret_cast<const uint4 *>(s->pool),
+                                                                       nch, s->st, s->bitmap);
     }
 }
 

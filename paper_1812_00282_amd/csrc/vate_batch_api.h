@@ -49,6 +49,8 @@ static BatchTune default_tune(uint32_t cus)
     t.grid_ingest = 8 * cus;
     t.grid_census = 4 * cus;
     t.grid_estimate = 8 * cus;
+    t.estimate_lanes = 1;
+    t.census_unroll = 1;
     return t;
 }
 
@@ -58,8 +60,19 @@ static void batch_phase(vate_batch *b, int ph, hipStream_t st)
     switch (ph) {
     case PH_PRESERVE: k_batch_preserve<<<t.grid_preserve, 256, 0, st>>>(b->items, b->S, b->tab); break;
     case PH_INGEST: k_batch_ingest<<<t.grid_ingest, 256, 0, st>>>(b->items, b->S, b->n_pairs, t, b->tab); break;
-    case PH_CENSUS: k_batch_census<<<t.grid_census, 256, 0, st>>>(b->items, b->S, t, b->tab); break;
-    default: k_batch_estimate<<<t.grid_estimate, t.estimate_block, 0, st>>>(b->items, b->S, t, b->tab); break;
+    case PH_CENSUS:
+        if (t.census_unroll == 4) k_batch_census<4><<<t.grid_census, 256, 0, st>>>(b->items, b->S, t, b->tab);
+        else if (t.census_unroll == 2) k_batch_census<2><<<t.grid_census, 256, 0, st>>>(b->items, b->S, t, b->tab);
+        else k_batch_census<1><<<t.grid_census, 256, 0, st>>>(b->items, b->S, t, b->tab);
+        break;
+    default:
+        if (t.estimate_lanes == 16)
+            k_batch_estimate<16><<<t.grid_estimate, t.estimate_block, 0, st>>>(b->items, b->S, t, b->tab);
+        else if (t.estimate_lanes == 4)
+            k_batch_estimate<4><<<t.grid_estimate, t.estimate_block, 0, st>>>(b->items, b->S, t, b->tab);
+        else
+            k_batch_estimate<1><<<t.grid_estimate, t.estimate_block, 0, st>>>(b->items, b->S, t, b->tab);
+        break;
     }
 }
 
@@ -74,7 +87,9 @@ static bool batch_tune_valid(const BatchTune &t)
     return t.ingest_tile >= 512 && t.ingest_tile % 512 == 0 && t.census_tile >= 256 && t.census_tile % 256 == 0 &&
            (t.estimate_block == 64 || t.estimate_block == 128 || t.estimate_block == 256) && t.grid_preserve >= 1 &&
            t.grid_ingest >= 1 && t.grid_census >= 1 && t.grid_estimate >= 1 && t.grid_preserve <= 65536 &&
-           t.grid_ingest <= 65536 && t.grid_census <= 65536 && t.grid_estimate <= 65536;
+           t.grid_ingest <= 65536 && t.grid_census <= 65536 && t.grid_estimate <= 65536 &&
+           (t.estimate_lanes == 1 || t.estimate_lanes == 4 || t.estimate_lanes == 16) &&
+           (t.census_unroll == 1 || t.census_unroll == 2 || t.census_unroll == 4);
 }
 
 extern "C" {
@@ -229,6 +244,8 @@ int vate_batch_get_tune(const vate_batch *b, vate_batch_tune *t)
     t->grid_ingest = b->tune.grid_ingest;
     t->grid_census = b->tune.grid_census;
     t->grid_estimate = b->tune.grid_estimate;
+    t->estimate_lanes = b->tune.estimate_lanes;
+    t->census_unroll = b->tune.census_unroll;
     return VATE_OK;
 }
 
@@ -243,6 +260,8 @@ int vate_batch_set_tune(vate_batch *b, const vate_batch_tune *t)
     n.grid_ingest = t->grid_ingest;
     n.grid_census = t->grid_census;
     n.grid_estimate = t->grid_estimate;
+    n.estimate_lanes = t->estimate_lanes;
+    n.census_unroll = t->census_unroll;
     if (!batch_tune_valid(n)) return bfail(b, VATE_E_INVAL, "invalid tuning parameters");
     b->tune = n;
     return VATE_OK;
@@ -291,29 +310,41 @@ int vate_batch_autotune(vate_batch *b, void *stream, char *report, size_t report
     };
     const char *names[PH_COUNT] = {"preserve", "ingest", "census", "estimate"};
     float best_ms[PH_COUNT] = {0.f, 1e30f, 1e30f, 1e30f};
+    // Per phase: tile size x a second axis x grid size (workgroups per CU).
+    // The second axis is the census's chunks in flight per thread and the
+    // estimate's lanes per host (how many lanes share one host's g gathers);
+    // the ingest has none.
+    const uint32_t tiles[3][3] = {{2048, 8192, 32768}, {1024, 4096, 16384}, {64, 128, 256}};
+    const uint32_t axis[3][3] = {{0, 0, 0}, {1, 2, 4}, {1, 4, 16}};
+    const uint32_t n_axis[3] = {1, 3, 3};
+    const uint32_t grids[3][4] = {{2, 4, 8, 16}, {2, 4, 8, 16}, {4, 8, 16, 32}};
     for (int ph = PH_INGEST; ph <= PH_ESTIMATE; ++ph) {
-        const uint32_t tiles[3][3] = {{2048, 8192, 32768}, {1024, 4096, 16384}, {64, 128, 256}};
-        const uint32_t grids[3][4] = {{2, 4, 8, 16}, {2, 4, 8, 16}, {4, 8, 16, 32}};
         for (int ti = 0; ti < 3; ++ti)
-            for (int gi = 0; gi < 4; ++gi) {
-                BatchTune cand = best;
-                const uint32_t tv = tiles[ph - 1][ti], gv = grids[ph - 1][gi] * C;
-                if (ph == PH_INGEST) { cand.ingest_tile = tv; cand.grid_ingest = gv; }
-                if (ph == PH_CENSUS) { cand.census_tile = tv; cand.grid_census = gv; }
-                if (ph == PH_ESTIMATE) { cand.estimate_block = tv; cand.grid_estimate = gv; }
-                float ms = 0.f;
-                int rc = time_phase(ph, cand, &ms);
-                if (rc != VATE_OK) return rc;
-                char buf[160];
-                snprintf(buf, sizeof(buf), "%s{\"phase\":\"%s\",\"tile\":%u,\"grid\":%u,\"ms\":%.5f}", first ? "" : ",",
-                         names[ph], tv, gv, ms);
-                first = false;
-                rep += buf;
-                if (ms < best_ms[ph]) {
-                    best_ms[ph] = ms;
-                    best = cand;
+            for (uint32_t ai = 0; ai < n_axis[ph - 1]; ++ai)
+                for (int gi = 0; gi < 4; ++gi) {
+                    BatchTune cand = best;
+                    const uint32_t tv = tiles[ph - 1][ti], av = axis[ph - 1][ai], gv = grids[ph - 1][gi] * C;
+                    if (ph == PH_INGEST) { cand.ingest_tile = tv; cand.grid_ingest = gv; }
+                    if (ph == PH_CENSUS) { cand.census_tile = tv; cand.census_unroll = av; cand.grid_census = gv; }
+                    if (ph == PH_ESTIMATE) { cand.estimate_block = tv; cand.estimate_lanes = av; cand.grid_estimate = gv; }
+                    float ms = 0.f;
+                    int rc = time_phase(ph, cand, &ms);
+                    if (rc != VATE_OK) {
+                        b->tune = best;
+                        (void)hipEventDestroy(e0);
+                        (void)hipEventDestroy(e1);
+                        return rc;
+                    }
+                    char buf[200];
+                    snprintf(buf, sizeof(buf), "%s{\"phase\":\"%s\",\"tile\":%u,\"%s\":%u,\"grid\":%u,\"ms\":%.5f}",
+                             first ? "" : ",", names[ph], tv, ph == PH_ESTIMATE ? "lanes" : "unroll", av, gv, ms);
+                    first = false;
+                    rep += buf;
+                    if (ms < best_ms[ph]) {
+                        best_ms[ph] = ms;
+                        best = cand;
+                    }
                 }
-            }
         b->tune = best;
     }
     // leave the slice's outputs as a plain slice would: tables, census, estimate
@@ -325,12 +356,14 @@ int vate_batch_autotune(vate_batch *b, void *stream, char *report, size_t report
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (e != hipSuccess) return bcheck(b, e, "autotune");
-    char buf[400];
+    char buf[480];
     snprintf(buf, sizeof(buf),
-             "],\"best\":{\"ingest_tile\":%u,\"grid_ingest\":%u,\"census_tile\":%u,\"grid_census\":%u,"
-             "\"estimate_block\":%u,\"grid_estimate\":%u,\"ms\":{\"ingest\":%.5f,\"census\":%.5f,\"estimate\":%.5f}}}",
-             best.ingest_tile, best.grid_ingest, best.census_tile, best.grid_census, best.estimate_block,
-             best.grid_estimate, best_ms[PH_INGEST], best_ms[PH_CENSUS], best_ms[PH_ESTIMATE]);
+             "],\"best\":{\"ingest_tile\":%u,\"grid_ingest\":%u,\"census_tile\":%u,\"census_unroll\":%u,"
+             "\"grid_census\":%u,\"estimate_block\":%u,\"estimate_lanes\":%u,\"grid_estimate\":%u,"
+             "\"ms\":{\"ingest\":%.5f,\"census\":%.5f,\"estimate\":%.5f}}}",
+             best.ingest_tile, best.grid_ingest, best.census_tile, best.census_unroll, best.grid_census,
+             best.estimate_block, best.estimate_lanes, best.grid_estimate, best_ms[PH_INGEST], best_ms[PH_CENSUS],
+             best_ms[PH_ESTIMATE]);
     rep += buf;
     if (report && report_len) snprintf(report, report_len, "%s", rep.c_str());
     if (b->has_graph) {   // the captured graph holds the old launch shapes

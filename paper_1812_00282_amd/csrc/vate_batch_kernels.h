@@ -31,8 +31,10 @@ struct BatchItem {
 struct BatchTune {
     uint32_t ingest_tile;        // packets per claimed tile (multiple of 512)
     uint32_t census_tile;        // pool chunks per claimed tile (multiple of 256)
-    uint32_t estimate_block;     // hosts per tile = threads per workgroup (64..256)
+    uint32_t estimate_block;     // threads per estimate workgroup (64, 128 or 256)
     uint32_t grid_preserve, grid_ingest, grid_census, grid_estimate;
+    uint32_t estimate_lanes;     // lanes per host (1, 4 or 16): hosts per tile = estimate_block / estimate_lanes
+    uint32_t census_unroll;      // pool chunks in flight per census thread (1, 2 or 4)
 };
 
 enum { PH_PRESERVE = 0, PH_INGEST = 1, PH_CENSUS = 2, PH_ESTIMATE = 3, PH_COUNT = 4 };
@@ -85,7 +87,8 @@ __global__ void k_batch_begin(BatchItem *__restrict__ items, uint32_t S, const u
         const unsigned long long np = min((unsigned long long)n_pairs[s], (unsigned long long)it.pairs_cap);
         tiles[PH_INGEST][s] = (np + tune.ingest_tile - 1) / tune.ingest_tile;
         tiles[PH_CENSUS][s] = (it.nchunks + tune.census_tile - 1) / tune.census_tile;
-        tiles[PH_ESTIMATE][s] = ((unsigned long long)it.n_hosts + tune.estimate_block - 1) / tune.estimate_block;
+        const uint32_t per_tile = tune.estimate_block / tune.estimate_lanes;
+        tiles[PH_ESTIMATE][s] = ((unsigned long long)it.n_hosts + per_tile - 1) / per_tile;
     }
     __syncthreads();
     if (threadIdx.x < PH_COUNT) {
@@ -173,19 +176,31 @@ __global__ void __launch_bounds__(256) k_batch_ingest(const BatchItem *__restric
     }
 }
 
-template <int W>
+template <int W, int U>
 __device__ __forceinline__ void batch_census_tile(const BatchItem &it, uint64_t c0, uint64_t c1, uint32_t *hist)
 {
     const uint32_t bact0 = it.st->bact0;
     const uint4 *pool4 = reinterpret_cast<const uint4 *>(it.pool);
-    const bool lds = it.G.k <= kBatchCensusBins;
-    for (uint64_t ch = c0 + threadIdx.x; ch < c1; ch += blockDim.x)
-        store_bits<W>(it.bitmap, ch, census_chunk<W>(it.G, pool4[ch], ch, bact0, lds ? hist : nullptr,
-                                                      census_of(it.st)));
+    const uint32_t pat = replicate<W>(inactive_value(it.G));
+    uint32_t *h = it.G.k <= kBatchCensusBins ? hist : nullptr;
+    for (uint64_t b = c0 + threadIdx.x; b < c1; b += U * blockDim.x) {
+        uint4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint64_t ch = b + (uint64_t)u * blockDim.x;
+            v[u] = ch < c1 ? pool4[ch] : make_uint4(pat, pat, pat, pat);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint64_t ch = b + (uint64_t)u * blockDim.x;
+            if (ch < c1) store_bits<W>(it.bitmap, ch, census_chunk_fast<W>(it.G, v[u], ch, bact0, pat, h, census_of(it.st)));
+        }
+    }
 }
 
 // The LDS histogram belongs to one sketch at a time: it is flushed into that
 // sketch's census when the claimed tiles move on to another sketch.
+template <int U>
 __global__ void __launch_bounds__(256) k_batch_census(const BatchItem *__restrict__ items, uint32_t S, BatchTune tune,
                                                       BatchTables *__restrict__ tab)
 {
@@ -209,24 +224,28 @@ __global__ void __launch_bounds__(256) k_batch_census(const BatchItem *__restric
         const BatchItem &it = items[s];
         const uint64_t c0 = (tile - tab->prefix[PH_CENSUS][s]) * tune.census_tile;
         const uint64_t c1 = min(c0 + tune.census_tile, it.nchunks);
-        if (it.width == 4) batch_census_tile<4>(it, c0, c1, hist);
-        else if (it.width == 8) batch_census_tile<8>(it, c0, c1, hist);
-        else batch_census_tile<16>(it, c0, c1, hist);
+        if (it.width == 4) batch_census_tile<4, U>(it, c0, c1, hist);
+        else if (it.width == 8) batch_census_tile<8, U>(it, c0, c1, hist);
+        else batch_census_tile<16, U>(it, c0, c1, hist);
     }
 }
 
-template <int W>
-__device__ __forceinline__ uint32_t batch_host_live(const BatchItem &it, uint32_t key, bool valid, uint32_t bact0)
+// Live VATs of one host counted by L lanes: lane `sub` of the host's L takes
+// VATs sub, sub + L, ... (kEstU gathers in flight), and the L partial counts
+// are summed across the lanes (every lane of the wavefront takes part).
+template <int W, int L>
+__device__ __forceinline__ uint32_t batch_host_live(const BatchItem &it, uint32_t key, bool valid, uint32_t bact0,
+                                                    uint32_t sub)
 {
     const Geo &G = it.G;
     const bool need_dist = it.kprime < G.k;
     uint32_t live = 0;
-    for (uint32_t i0 = 0; i0 < G.g; i0 += kEstU) {
+    for (uint32_t i0 = sub; i0 < G.g; i0 += L * kEstU) {
         uint32_t pid[kEstU], byte[kEstU];
 #pragma unroll
-        for (int u = 0; u < kEstU; ++u) pid[u] = vat_pid(G, key, i0 + u);
+        for (int u = 0; u < kEstU; ++u) pid[u] = vat_pid(G, key, i0 + u * L);
 #pragma unroll
-        for (int u = 0; u < kEstU; ++u) byte[u] = (valid && i0 + u < G.g) ? it.bitmap[pid[u] >> 3] : 0u;
+        for (int u = 0; u < kEstU; ++u) byte[u] = (valid && i0 + u * L < G.g) ? it.bitmap[pid[u] >> 3] : 0u;
 #pragma unroll
         for (int u = 0; u < kEstU; ++u) {
             if (!((byte[u] >> (pid[u] & 7u)) & 1u)) continue;
@@ -238,13 +257,17 @@ __device__ __forceinline__ uint32_t batch_host_live(const BatchItem &it, uint32_
             live += d < it.kprime;
         }
     }
+#pragma unroll
+    for (int off = 1; off < L; off <<= 1) live += __shfl_xor(live, off, 64);
     return live;
 }
 
+template <int L>
 __global__ void __launch_bounds__(256) k_batch_estimate(const BatchItem *__restrict__ items, uint32_t S,
                                                         BatchTune tune, BatchTables *__restrict__ tab)
 {
     const unsigned long long total = tab->prefix[PH_ESTIMATE][S];
+    const uint32_t per_tile = blockDim.x / L, sub = threadIdx.x % L;
     for (;;) {
         const unsigned long long tile = claim_tile(&tab->claim[PH_ESTIMATE]);
         if (tile >= total) break;
@@ -252,14 +275,14 @@ __global__ void __launch_bounds__(256) k_batch_estimate(const BatchItem *__restr
         const BatchItem &it = items[s];
         const uint64_t active_pool = pool_active(it.st, it.kprime);
         const uint32_t bact0 = it.st->bact0;
-        const uint64_t h = (tile - tab->prefix[PH_ESTIMATE][s]) * tune.estimate_block + threadIdx.x;
+        const uint64_t h = (tile - tab->prefix[PH_ESTIMATE][s]) * per_tile + threadIdx.x / L;
         const bool valid = h < it.n_hosts;
         const uint32_t key = host_key(it.G, valid ? it.hosts[h] : 0u);
         uint32_t live;
-        if (it.width == 4) live = batch_host_live<4>(it, key, valid, bact0);
-        else if (it.width == 8) live = batch_host_live<8>(it, key, valid, bact0);
-        else live = batch_host_live<16>(it, key, valid, bact0);
-        if (valid) {
+        if (it.width == 4) live = batch_host_live<4, L>(it, key, valid, bact0, sub);
+        else if (it.width == 8) live = batch_host_live<8, L>(it, key, valid, bact0, sub);
+        else live = batch_host_live<16, L>(it, key, valid, bact0, sub);
+        if (valid && sub == 0) {
             it.est[h] = estimate_from_counts(it.G.g - live, it.G.N - active_pool, it.G.g, it.G.c);
             if (it.live) it.live[h] = live;
         }

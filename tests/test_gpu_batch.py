@@ -185,6 +185,52 @@ def test_batch_autotune_keeps_results():
     counts = lambda s: streams.batch_packet_counts(5, len(members), s, lo=3.0, hi=5.0)
     _, report = _run_pair(members, 5, counts, graph=True, tune_at=1)
     assert "best" in report and report["tune"]["estimate_block"] in (64, 128, 256)
+    assert report["tune"]["estimate_lanes"] in (1, 4, 16) and report["tune"]["census_unroll"] in (1, 2, 4)
+    # every (tile, second axis, grid) candidate of the three tuned phases was timed
+    assert len(report["candidates"]) == 12 + 36 + 36
+
+
+def test_batch_tune_cache(tmp_path):
+    """A choice stored in the JSON cache under the batch geometry is set
+    again, without timing, for a batch of the same geometry; another geometry
+    is tuned afresh; the cached shapes still give the oracle's results."""
+    members = _members_small()[:6]
+    counts = lambda s: streams.batch_packet_counts(7, len(members), s, lo=3.0, hi=5.0)
+    cache = str(tmp_path / "tune.json")
+    dev = torch.device("cuda")
+
+    def run(ms, n_slices):
+        cfgs = [Config(m.log2_pool, m.width, m.k, m.g, 0, m.seed, m.seed + 1) for m in ms]
+        hosts = [torch.randint(-2**31, 2**31, (m.n_hosts,), device=dev, dtype=torch.int64).to(torch.int32)
+                 for m in ms]
+        cs = [counts(s)[: len(ms)] for s in range(n_slices)]
+        b = Batch([Sketch(c) for c in cfgs], [int(max(c[i] for c in cs)) for i in range(len(ms))], hosts)
+        refs = [OracleSketch(c.log2_pool, c.width, c.k, c.g, c.seed_a, c.seed_b, c.partition) for c in cfgs]
+        rep = None
+        for s in range(n_slices):
+            sl = [streams.member_slice_torch(m, hosts[i], s, int(cs[s][i]), dev) for i, m in enumerate(ms)]
+            b.load(sl)
+            b.slice()
+            b.synchronize()
+            if s == 0:
+                rep = b.autotune(cache=cache)
+                b.synchronize()
+            for i, r in enumerate(refs):
+                r.ingest(sl[i].cpu().numpy().view(np.uint32))
+                r.close_slice()
+        hn = [h.cpu().numpy().view(np.uint32) for h in hosts]
+        for i, r in enumerate(refs):
+            _check_oracle(b.sketches[i], b.est[i], b.live[i], r, hn[i], np.arange(hn[i].size), f"member {i}")
+        return b, rep
+
+    b1, r1 = run(members, 3)
+    assert r1["cached"] is False and r1["key"] == b1.geometry_key()
+    b2, r2 = run(members, 3)
+    assert r2["cached"] is True and r2["tune"] == r1["tune"]
+    _, r3 = run(members[:5], 2)
+    assert r3["cached"] is False
+    import json
+    assert set(json.load(open(cache))) == {r1["key"], r3["key"]}
 
 
 def test_batch_two_tunings_match_oracle():
@@ -194,9 +240,11 @@ def test_batch_two_tunings_match_oracle():
     members = _members_small()[:10]
     counts = lambda s: streams.batch_packet_counts(6, len(members), s, lo=3.0, hi=5.0)
     small = {"ingest_tile": 512, "census_tile": 256, "estimate_block": 64, "grid_preserve": 7,
-             "grid_ingest": 13, "grid_census": 11, "grid_estimate": 9}
+             "grid_ingest": 13, "grid_census": 11, "grid_estimate": 9, "estimate_lanes": 16,
+             "census_unroll": 4}
     large = {"ingest_tile": 32768, "census_tile": 16384, "estimate_block": 256, "grid_preserve": 512,
-             "grid_ingest": 4096, "grid_census": 2048, "grid_estimate": 8192}
+             "grid_ingest": 4096, "grid_census": 2048, "grid_estimate": 8192, "estimate_lanes": 4,
+             "census_unroll": 2}
     _run_pair(members, 8, counts, graph=True, tunes={0: small, 4: large})
 
 

@@ -409,14 +409,16 @@ def test_multi_window_estimates(w, k, c):
     (18, 8, 5, 3, 0, 2500),         # g = 3
     (23, 7, 60, 1024, 0, 300),      # exact 7-bit ATs
     (21, 10, 300, 512, 1, 500),     # exact 10-bit ATs, 16-bit distances
-    (20, 8, 12, 100, 0, 200_000),   # 655 hosts per subgroup, 306 subgroups: persistent scatter
-                                    # workgroups, ragged last one, v / g by multiply-high
-    (24, 8, 60, 1024, 0, 20_000),   # 63 hosts per subgroup (the 16-bit sort's limit), 318
-                                    # subgroups, each slice's walk split over two workgroups
-    (22, 4, 7, 100, 1, 200_000),    # 4-bit ATs, low-deviation partition, 306 subgroups
+    (20, 8, 12, 100, 0, 200_000),   # 405 hosts per subgroup, 494 subgroups: most persistent scatter
+                                    # workgroups take two, ragged last one, v / g by multiply-high
+    (24, 8, 60, 1024, 0, 20_000),   # 39 hosts per subgroup, 513 subgroups: every scatter workgroup
+                                    # takes two or more; 16 slices (XCD mapping)
+    (22, 4, 7, 100, 1, 200_000),    # 4-bit ATs, low-deviation partition, 494 subgroups
     (21, 16, 129, 64, 0, 100_000),  # 16-bit ATs, 252 hosts per subgroup, 397 subgroups
     (23, 10, 300, 256, 0, 50_000),  # exact 10-bit ATs, 108 hosts per subgroup, 463 subgroups
-    (26, 8, 40, 1024, 0, 40_000),   # 64 slices, 635 subgroups: slice walks split in four (XCD mapping)
+    (26, 8, 40, 1024, 0, 40_000),   # 64 slices (XCD mapping), 1026 subgroups: four per scatter workgroup
+    (20, 8, 60, 1024, 0, 100_000),  # one slice, 2565 subgroups: the slice's walk split over two workgroups
+    (23, 8, 60, 1024, 0, 100_000),  # 8 slices (XCD mapping), each walk split over two workgroups
     (12, 8, 9, 64, 0, 4000),        # a pool of 4096 ATs (one slice of 128 activity words), dense hits
 ])
 def test_partitioned_geometries(c, w, k, g, partition, n_hosts):
