@@ -89,7 +89,8 @@ typedef struct vate_params {
 typedef struct vate_sketch vate_sketch;
 
 /* Device memory a sketch needs: the pool (N*width/8 bytes, 256-byte aligned)
- * and a state block (clock t, BACT^0, flags, pool census; 256-byte aligned).
+ * and a state block (clock t, BACT^0, flags, pool census, the activity
+ * bitmap of N bits, 16 partial censuses of k counters; 256-byte aligned).
  * Validates *p.  Returns VATE_OK or VATE_E_INVAL. */
 int vate_state_bytes(const vate_params *p, size_t *pool_bytes, size_t *state_bytes);
 

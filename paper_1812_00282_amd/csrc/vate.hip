@@ -58,11 +58,26 @@ static size_t bitmap_offset(uint32_t k)
     return (b + 255) & ~size_t(255);
 }
 
-static size_t state_bytes_for(uint32_t k, uint64_t N)
+static size_t bitmap_bytes(uint64_t N)
 {
     size_t bm = (size_t)((N + 7) / 8);
-    if (bm < 16) bm = 16;
-    return (bitmap_offset(k) + bm + 255) & ~size_t(255);
+    return bm < 16 ? 16 : bm;
+}
+
+// After the bitmap: kCensusCopies partial censuses (k counters each) that
+// k_census8's workgroups add into, so that no counter takes an atomic from
+// every workgroup; k_census_fold then adds them to the census and clears
+// them (they are zero between censuses).
+constexpr uint32_t kCensusCopies = 16;
+
+static size_t copies_offset(uint32_t k, uint64_t N)
+{
+    return (bitmap_offset(k) + bitmap_bytes(N) + 255) & ~size_t(255);
+}
+
+static size_t state_bytes_for(uint32_t k, uint64_t N)
+{
+    return (copies_offset(k, N) + 8ull * kCensusCopies * k + 255) & ~size_t(255);
 }
 
 // ---------------------------------------------------------------------------
@@ -182,7 +197,7 @@ __host__ __device__ __forceinline__ uint32_t replicate(uint32_t val)
 // ---------------------------------------------------------------------------
 template <int W>
 __global__ void __launch_bounds__(256) k_init(Geo G, uint4 *__restrict__ pool4, uint64_t nchunks,
-                                              DevState *__restrict__ st)
+                                              DevState *__restrict__ st, unsigned long long *__restrict__ copies)
 {
     const uint32_t pat = replicate<W>(inactive_value(G));
     const uint4 v = make_uint4(pat, pat, pat, pat);
@@ -194,6 +209,7 @@ __global__ void __launch_bounds__(256) k_init(Geo G, uint4 *__restrict__ pool4, 
             st->bact0 = 0;
         }
         for (uint32_t d = threadIdx.x; d < G.k; d += blockDim.x) census_of(st)[d] = 0;
+        for (uint32_t d = threadIdx.x; d < kCensusCopies * G.k; d += blockDim.x) copies[d] = 0;
     }
 }
 
@@ -443,7 +459,8 @@ constexpr uint32_t kCensus8Bins = 256;
 constexpr int kCensus8U = 4;   // chunks per lane and round
 
 __global__ void __launch_bounds__(256) k_census8(Geo G, const uint4 *__restrict__ pool4, uint64_t nchunks,
-                                                 DevState *__restrict__ st, uint8_t *__restrict__ bitmap)
+                                                 DevState *__restrict__ st, uint8_t *__restrict__ bitmap,
+                                                 unsigned long long *__restrict__ copies)
 {
     constexpr int U = kCensus8U;
     __shared__ uint32_t hist[kCensus8Bins];
@@ -491,8 +508,24 @@ __global__ void __launch_bounds__(256) k_census8(Geo G, const uint4 *__restrict_
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
     __syncthreads();
+    // Flush into copy blockIdx mod kCensusCopies (k_census_fold adds the
+    // copies to the census).
+    unsigned long long *mine = copies + (size_t)(blockIdx.x % kCensusCopies) * G.k;
     for (uint32_t d = threadIdx.x; d < G.k; d += blockDim.x)
-        if (hist[d]) atomicAdd(&census_of(st)[d], (unsigned long long)hist[d]);
+        if (hist[d]) atomicAdd(&mine[d], (unsigned long long)hist[d]);
+}
+
+__global__ void __launch_bounds__(256) k_census_fold(Geo G, DevState *__restrict__ st,
+                                                     unsigned long long *__restrict__ copies)
+{
+    for (uint32_t d = blockIdx.x * blockDim.x + threadIdx.x; d < G.k; d += gridDim.x * blockDim.x) {
+        unsigned long long sum = 0;
+        for (uint32_t c = 0; c < kCensusCopies; ++c) {
+            sum += copies[(size_t)c * G.k + d];
+            copies[(size_t)c * G.k + d] = 0;
+        }
+        census_of(st)[d] += sum;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -872,6 +905,7 @@ struct vate_sketch {
     uint8_t *pool;
     DevState *st;
     uint8_t *bitmap;             // activity bitmap inside the state block
+    unsigned long long *copies;  // k_census8's partial censuses inside the state block
     size_t pool_bytes, state_bytes;
     uint64_t max_block_chunks;   // chunks a due block can overlap
     int closed;                  // 1: slice ended, estimates allowed
@@ -929,7 +963,8 @@ static void launch_init(vate_sketch *s, hipStream_t st)
         k_init_x<<<grid_for(ng, 256, 8192), 256, 0, st>>>(s->G, reinterpret_cast<uint32_t *>(s->pool), ng, s->st);
     } else {
         uint64_t nch = s->pool_bytes / 16;
-        k_init<W><<<grid_for(nch, 256, 8192), 256, 0, st>>>(s->G, reinterpret_cast<uint4 *>(s->pool), nch, s->st);
+        k_init<W><<<grid_for(nch, 256, 8192), 256, 0, st>>>(s->G, reinterpret_cast<uint4 *>(s->pool), nch, s->st,
+                                                             s->copies);
     }
 }
 
@@ -942,12 +977,14 @@ static void launch_census(vate_sketch *s, hipStream_t st)
                                                              s->st, s->bitmap);
     } else {
         uint64_t nch = s->pool_bytes / 16;
-        if (W == 8 && s->G.k <= kCensus8Bins)
+        if (W == 8 && s->G.k <= kCensus8Bins) {
             k_census8<<<grid_for(nch, 256 * kCensus8U, 2048), 256, 0, st>>>(
-                s->G, reinterpret_cast<const uint4 *>(s->pool), nch, s->st, s->bitmap);
-        else
+                s->G, reinterpret_cast<const uint4 *>(s->pool), nch, s->st, s->bitmap, s->copies);
+            k_census_fold<<<1, 256, 0, st>>>(s->G, s->st, s->copies);
+        } else {
             k_census<W><<<grid_for(nch, 256 * 4, 2048), 256, 0, st>>>(s->G, reinterpret_cast<const uint4 *>(s->pool),
                                                                        nch, s->st, s->bitmap);
+        }
     }
 }
 
@@ -1241,6 +1278,7 @@ int vate_create(const vate_params *p, void *pool_dev, void *state_dev, void *str
     s->pool_bytes = (size_t)(G.N * p->width / 8);
     s->state_bytes = state_bytes_for(p->k, G.N);
     s->bitmap = static_cast<uint8_t *>(state_dev) + bitmap_offset(p->k);
+    s->copies = reinterpret_cast<unsigned long long *>(static_cast<uint8_t *>(state_dev) + copies_offset(p->k, G.N));
     uint64_t maxb = 0;
     for (uint32_t i = 0; i < G.twok; ++i)
         maxb = std::max<uint64_t>(maxb, block_start(G, i + 1) - block_start(G, i));

@@ -47,6 +47,7 @@ constexpr uint32_t kSliceLog2 = 20;                             // ATs per slice
 constexpr uint32_t kRunMaxSlices = 4096;                        // any pool up to 2^32 ATs
 constexpr uint32_t kRunMaxHosts = 1024;                         // hosts per subgroup
 constexpr uint32_t kFinThreads = 256;
+constexpr uint32_t kFinB = 4;                                   // live-result pieces per finalize thread at a time
 constexpr uint32_t kLookU = 8;                                  // 16-byte entry chunks per lane and lookup pass
 constexpr uint32_t kFinHistBytes = 64u * 1024u;                 // per-subgroup histogram ceiling
 constexpr uint32_t kFinRunBytes = 8u * (kRunMaxSlices + 1u);    // run cells and chunk prefix in the finalize
@@ -606,25 +607,40 @@ __global__ void __launch_bounds__(kFinThreads, 5) k_run_finalize(Geo G, PartGeo 
         // pre[r + 1]; each is counted into its host's bin with an LDS atomic.
         // Bin k (inactive) is not counted: it is g minus the others, filled
         // in below.
-        for (uint32_t c = t; c < total; c += kFinThreads) {
-            uint32_t lo = 0, hi = nr;                // largest r with pre[r] <= c
-            while (hi - lo > 1) {
-                const uint32_t mid = (lo + hi) >> 1;
-                if (pre[mid] <= c) lo = mid; else hi = mid;
-            }
-            const uint32_t k4 = c - pre[lo];
-            const uint32_t cb = cell[lo];
-            const uint32_t sg = lo / ns;
-            const uint32_t nv = min(4u, (cb >> 16) - 4u * k4);
-            const uint4 w4 = reinterpret_cast<const uint4 *>(hits + (size_t)(s0 + sg) * PG.region)[(cb & 0xFFFFu) + k4];
-            const uint32_t hrow = sg * PG.hosts;
+        // kFinB pieces per thread at a time: their runs found, their loads
+        // issued together, then their counts.
+        for (uint32_t c0 = t; c0 < total; c0 += kFinB * kFinThreads) {
+            uint4 w4[kFinB];
+            uint32_t nv[kFinB], hrow[kFinB];
 #pragma unroll
-            for (uint32_t m = 0; m < 4; ++m) {
-                if (m >= nv) break;
-                const uint32_t r = comp4(w4, m), d = r & 0xFFFFu;
-                if (d >= G.k) continue;
-                atomicAdd(&hist[(hrow + (r >> 16)) * rowp + (d >> 1)], 1u << ((d & 1u) << 4));
+            for (uint32_t b = 0; b < kFinB; ++b) {
+                const uint32_t c = c0 + b * kFinThreads;
+                nv[b] = 0;
+                hrow[b] = 0;
+                w4[b] = make_uint4(0, 0, 0, 0);
+                if (c < total) {
+                    uint32_t lo = 0, hi = nr;        // largest r with pre[r] <= c
+                    while (hi - lo > 1) {
+                        const uint32_t mid = (lo + hi) >> 1;
+                        if (pre[mid] <= c) lo = mid; else hi = mid;
+                    }
+                    const uint32_t k4 = c - pre[lo];
+                    const uint32_t cb = cell[lo];
+                    const uint32_t sg = lo / ns;
+                    nv[b] = min(4u, (cb >> 16) - 4u * k4);
+                    hrow[b] = sg * PG.hosts;
+                    w4[b] = reinterpret_cast<const uint4 *>(hits + (size_t)(s0 + sg) * PG.region)[(cb & 0xFFFFu) + k4];
+                }
             }
+#pragma unroll
+            for (uint32_t b = 0; b < kFinB; ++b)
+#pragma unroll
+                for (uint32_t m = 0; m < 4; ++m) {
+                    if (m >= nv[b]) break;
+                    const uint32_t r = comp4(w4[b], m), d = r & 0xFFFFu;
+                    if (d >= G.k) continue;
+                    atomicAdd(&hist[(hrow[b] + (r >> 16)) * rowp + (d >> 1)], 1u << ((d & 1u) << 4));
+                }
         }
     }
     __syncthreads();
@@ -683,18 +699,25 @@ __global__ void __launch_bounds__(kFinThreads, 5) k_run_finalize(Geo G, PartGeo 
         const float occupancy = (float)active_pool / (float)G.N;
         const uint32_t w = t >> 6;
         for (uint32_t base = 0; base < nh; base += kFinThreads / 4) {
-            if (t < kFinThreads / 4) {
+            {   // live count and closed form of host base + t / 4, four threads a host
+                const uint32_t hh = t >> 2, qq = t & 3u;
                 uint32_t live = 0;
-                float cf = 0.f;
-                if (base + t < nh) {
-                    const uint32_t *row = hist + (base + t) * rowp;
-                    for (uint32_t j = 0; j < G.k / 2; ++j) live += (row[j] & 0xFFFFu) + (row[j] >> 16);
-                    if (G.k & 1u) live += row[G.k / 2] & 0xFFFFu;
-                    cf = estimate_from_counts(G.g - live, G.N - active_pool, G.g, G.c);
-                    cf_out[h0 + base + t] = cf;
+                if (base + hh < nh) {
+                    const uint32_t *row = hist + (base + hh) * rowp;
+                    for (uint32_t j = qq; j < G.k / 2; j += 4) live += (row[j] & 0xFFFFu) + (row[j] >> 16);
+                    if (qq == 0 && (G.k & 1u)) live += row[G.k / 2] & 0xFFFFu;
                 }
-                cf_s[t] = cf;
-                live_s[t] = live;
+                live += __shfl_xor(live, 1, 64);
+                live += __shfl_xor(live, 2, 64);
+                if (qq == 0) {
+                    float cf = 0.f;
+                    if (base + hh < nh) {
+                        cf = estimate_from_counts(G.g - live, G.N - active_pool, G.g, G.c);
+                        cf_out[h0 + base + hh] = cf;
+                    }
+                    cf_s[hh] = cf;
+                    live_s[hh] = live;
+                }
             }
             __syncthreads();
             const uint32_t m0 = base + 16 * w;
