@@ -173,7 +173,7 @@ int vate_estimate_ws(vate_sketch *s, const uint32_t *hosts_dev, size_t n_hosts,
  * vate_estimate_ws.  Every call on one GPU shares that GPU's array, which
  * keeps the last call's contents: calls that overlap on one GPU (from any
  * sketch, stream or host thread) race and must not be issued.  The host
- * count is limited by the array: at g = 1024 about 8,000 hosts.
+ * count is limited by the array: at g = 1024 on a 2^28 pool about 7,900 hosts.
  * Errors: as vate_estimate_ws; VATE_E_INVAL when the host count needs more
  * workspace than VATE_NOALLOC_SCRATCH_BYTES (vate_estimate_workspace_bytes
  * tells); VATE_E_DEVICE if the array's device address cannot be found. */

@@ -1119,13 +1119,13 @@ static bool part_geo(const vate_sketch *s, uint64_t n, PartGeo *out)
     p.fast = G.a >= (1ull << sl) ? 1u : 0u;
     // Subgroups per finalize workgroup: the network takes hosts in tiles of
     // 64, so the count whose hosts leave the least of their last tile empty
-    // (the fewest on a tie), as long as the histograms and run cells fit.
+    // (the fewest on a tie), as long as the histograms fit.
     {
         uint32_t best = 1;
         double waste = 1e30;
         for (uint32_t f = 1; f <= 16; ++f) {
             const uint64_t fh = f * hosts;
-            if (fh * 4ull * p.rowp > kFinHistBytes || (uint64_t)f * ns > kRunMaxSlices) break;
+            if (fh * 4ull * p.rowp > kFinHistBytes) break;
             const double w = (double)(((fh + 63) / 64) * 64 - fh) / (double)fh;
             if (w < waste - 1e-9) waste = w, best = f;
         }
@@ -1143,7 +1143,7 @@ static bool part_geo(const vate_sketch *s, uint64_t n, PartGeo *out)
         p.lds_lookup = (fixed + (p.dist_cap << p.dist16) + 15u) & ~15u;
         if (p.lds_lookup > s->lds_budget) p.lds_lookup = s->lds_budget & ~15u, p.dist_cap = (p.lds_lookup - fixed) >> p.dist16;
     }
-    p.lds_final = p.fgroup * p.hosts * p.rowp * 4u + 8u * p.fgroup * (uint32_t)ns + 4u;
+    p.lds_final = p.fgroup * p.hosts * p.rowp * 4u + 4u;
     // Each slice's walk over the subgroups is cut into ranges, one workgroup
     // each, so that the launch has at least one workgroup per CU (each builds
     // its slice's LDS tables once); a range is a whole number of 64-subgroup
@@ -1165,6 +1165,7 @@ struct RunWs {
     uint32_t *entries;          // [n_sub][region] sorted entries
     uint32_t *hits;             // [n_sub][region] live results (host << 16 | distance), packed at the front of each run's slots
     uint32_t *table;            // [n_sub][n_slices + 1] run starts and live counts
+    uint32_t *heads;            // [n_sub][n_slices][4] each run's first four live results
     unsigned long long *cum;    // [k + 1] census prefix (several windows)
     size_t bytes;
 };
@@ -1181,6 +1182,8 @@ static RunWs run_ws(const PartGeo &pg, uint32_t k, void *base)
     off += align256(ents * 4);
     w.table = reinterpret_cast<uint32_t *>(p + off);
     off += align256((size_t)pg.n_sub * (pg.n_slices + 1) * 4);
+    w.heads = reinterpret_cast<uint32_t *>(p + off);
+    off += align256((size_t)pg.n_sub * pg.n_slices * 16);
     w.cum = reinterpret_cast<unsigned long long *>(p + off);
     off += align256((size_t)(k + 1) * 8);
     w.bytes = off;
@@ -1214,7 +1217,7 @@ static int launch_part(vate_sketch *s, const PartGeo &pg, void *ws, const uint32
         if (rc == VATE_OK)
             rc = set_lds_limit(s, reinterpret_cast<const void *>(&k_run_lookup<W>), s->lds_budget);
         if (rc == VATE_OK)
-            rc = set_lds_limit(s, reinterpret_cast<const void *>(&k_run_finalize<MODE>), kFinHistBytes + kFinRunBytes);
+            rc = set_lds_limit(s, reinterpret_cast<const void *>(&k_run_finalize<MODE>), kFinHistBytes + 16u);
         if (rc != VATE_OK) return rc;
         attr_set.fetch_or(bit, std::memory_order_release);
     }
@@ -1224,10 +1227,11 @@ static int launch_part(vate_sketch *s, const PartGeo &pg, void *ws, const uint32
                                                                                        w.table);
     if (steps == PART_PLAN) return VATE_OK;
     k_run_lookup<W><<<pg.n_slices * pg.split, kRunThreads, pg.lds_lookup, st>>>(
-        s->G, pg, s->pool, reinterpret_cast<const uint32_t *>(s->bitmap), s->st, w.entries, w.table, w.hits);
+        s->G, pg, s->pool, reinterpret_cast<const uint32_t *>(s->bitmap), s->st, w.entries, w.table, w.hits,
+        w.heads);
     if (MODE == kFinMulti) k_census_prefix<<<1, 64, 0, st>>>(s->G, s->st, w.cum);
     k_run_finalize<MODE><<<(pg.n_sub + pg.fgroup - 1) / pg.fgroup, kFinThreads, pg.lds_final, st>>>(
-        s->G, pg, s->st, n, kprime, w.hits, w.table, est, live, hist, win, w.cum,
+        s->G, pg, s->st, n, kprime, w.hits, w.heads, w.table, est, live, hist, win, w.cum,
         static_cast<const mlp::Packed *>(weights), cf);
     return VATE_OK;
 }

@@ -27,17 +27,20 @@
 //                 flat list of chunks and tests every entry's bit; only the
 //                 live ones (active for window k: about 1 % of the VATs in the
 //                 40 Gb/s steady state) take a slot of their run from an LDS
-//                 counter and write (host within subgroup, distance) there,
-//                 in the entries' own positions of the result array.  The
-//                 run's live count goes beside its start in the table.
+//                 counter and write (host within subgroup, distance): the
+//                 run's first four into its 16-byte cell of a dense
+//                 [subgroup][slice] array, any more into the entries' own
+//                 positions of the result array.  The run's live count goes
+//                 beside its start in the table.
 //  k_run_finalize a few subgroups per workgroup.  Reads the live results of
-//                 their runs, builds each host's distance histogram in LDS
+//                 their runs (a subgroup's cells are contiguous, so mostly
+//                 whole lines), builds each host's distance histogram in LDS
 //                 (the inactive bin k is g minus the rest) and forms Eq. 11 for
 //                 k', several windows, or the learned estimate (the network
 //                 fed from the LDS histograms, 16 hosts per wavefront).
 //
 // HBM traffic per VAT: the 4-byte entry written and read back once; per live
-// VAT 4 bytes of result written and read back.
+// VAT 4 bytes of result written and read back (in 16-byte run cells).
 
 constexpr uint32_t kRunThreads = 1024;                          // scatter / lookup workgroup
 constexpr uint32_t kRunPerThread = 40;                          // VATs hashed per scatter thread (pids held in registers)
@@ -47,10 +50,8 @@ constexpr uint32_t kSliceLog2 = 20;                             // ATs per slice
 constexpr uint32_t kRunMaxSlices = 4096;                        // any pool up to 2^32 ATs
 constexpr uint32_t kRunMaxHosts = 1024;                         // hosts per subgroup
 constexpr uint32_t kFinThreads = 256;
-constexpr uint32_t kFinB = 4;                                   // live-result pieces per finalize thread at a time
 constexpr uint32_t kLookU = 8;                                  // 16-byte entry chunks per lane and lookup pass
 constexpr uint32_t kFinHistBytes = 64u * 1024u;                 // per-subgroup histogram ceiling
-constexpr uint32_t kFinRunBytes = 8u * (kRunMaxSlices + 1u);    // run cells and chunk prefix in the finalize
 
 struct PartGeo {
     uint32_t sl;          // ATs per slice = 2^sl
@@ -255,7 +256,8 @@ __global__ void __launch_bounds__(kRunThreads) k_run_lookup(Geo G, PartGeo PG, c
                                                            const uint32_t *__restrict__ bitmap,
                                                            const DevState *__restrict__ st,
                                                            const uint32_t *__restrict__ entries,
-                                                           uint32_t *__restrict__ table, uint32_t *__restrict__ hits_out)
+                                                           uint32_t *__restrict__ table, uint32_t *__restrict__ hits_out,
+                                                           uint32_t *__restrict__ heads)
 {
     // LDS: the slice's activity bits (then zero words up to a whole block and
     // the padding entries' sentinel word), the rank tables, one live-result
@@ -450,7 +452,11 @@ __global__ void __launch_bounds__(kRunThreads) k_run_lookup(Geo G, PartGeo PG, c
                                                                : (uint32_t)dist8[live_rank(bm, sup, blk, o)])
                                                   : dist_at(o);
                         const uint32_t slot = atomicAdd(&cnt[j], 1u);
-                        hits_out[(size_t)(s0 + j) * PG.region + 4u * Sj + slot] = ((e >> (sl + 1)) << 16) | d;
+                        const uint32_t val = ((e >> (sl + 1)) << 16) | d;
+                        if (slot < 4u)
+                            heads[((size_t)(s0 + j) * PG.n_slices + b) * 4u + slot] = val;
+                        else
+                            hits_out[(size_t)(s0 + j) * PG.region + 4u * Sj + (slot - 4u)] = val;
                     }
                 }
             }
@@ -535,6 +541,7 @@ template <int MODE>
 __global__ void __launch_bounds__(kFinThreads, 5) k_run_finalize(Geo G, PartGeo PG, const DevState *__restrict__ st,
                                                              uint32_t n, uint32_t kprime,
                                                              const uint32_t *__restrict__ hits,
+                                                             const uint32_t *__restrict__ heads,
                                                              const uint32_t *__restrict__ table, float *__restrict__ est,
                                                              uint32_t *__restrict__ live_out,
                                                              uint32_t *__restrict__ hist_out, Windows win,
@@ -542,11 +549,8 @@ __global__ void __launch_bounds__(kFinThreads, 5) k_run_finalize(Geo G, PartGeo 
                                                              const mlp::Packed *__restrict__ P,
                                                              float *__restrict__ cf_out)
 {
-    // [hosts][rowp] packed 16-bit bins of the workgroup's fgroup subgroups,
-    // then their run cells and the prefix of their live entries in 4-entry
-    // pieces (run r is slice r mod n_slices of subgroup s0 + r / n_slices)
+    // [hosts][rowp] packed 16-bit bins of the workgroup's fgroup subgroups
     extern __shared__ __attribute__((aligned(16))) uint32_t hist[];
-    __shared__ uint32_t wtot[kFinThreads / 64];
     const uint32_t t = threadIdx.x;
     const uint32_t s0 = blockIdx.x * PG.fgroup;
     const uint32_t nsg = min(PG.fgroup, PG.n_sub - s0);
@@ -554,93 +558,36 @@ __global__ void __launch_bounds__(kFinThreads, 5) k_run_finalize(Geo G, PartGeo 
     const uint32_t nh = min(nsg * PG.hosts, n - h0);
     const uint32_t rowp = PG.rowp;
     const uint32_t ns = PG.n_slices, nr = nsg * ns;
-    uint32_t *cell = hist + nh * rowp;          // [nr] run cells
-    uint32_t *pre = cell + nr;                  // [nr + 1] pieces before run r
     for (uint32_t q = t; q < nh * rowp; q += kFinThreads) hist[q] = 0;
-    // Exclusive prefix of the runs' piece counts: thread t owns runs
-    // [t rs, (t+1) rs).  (A live count never exceeds the run's slots; the
-    // clamp keeps every read inside them whatever the table holds.)
-    const uint32_t rs = (nr + kFinThreads - 1) / kFinThreads;
-    auto cell_of = [&](uint32_t r, uint32_t &next) {
-        const uint32_t *trow = table + (size_t)(s0 + r / ns) * (ns + 1);
-        const uint32_t b = r % ns;
-        next = trow[b + 1] & 0xFFFFu;
-        return trow[b];
-    };
-    uint32_t mine = 0;
-    for (uint32_t q = 0; q < rs; ++q) {
-        const uint32_t r = t * rs + q;
-        if (r < nr) {
-            uint32_t next;
-            const uint32_t c = cell_of(r, next);
-            const uint32_t np = min(((c >> 16) + 3u) >> 2, next - (c & 0xFFFFu));
-            cell[r] = (c & 0xFFFFu) | (min(c >> 16, 4u * np) << 16);
-            mine += np;
-        }
-    }
-    const uint32_t lane = t & 63u, wv = t >> 6;
-    uint32_t incl = mine;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const uint32_t y = __shfl_up(incl, off, 64);
-        if (lane >= (uint32_t)off) incl += y;
-    }
-    if (lane == 63) wtot[wv] = incl;
-    __syncthreads();
-    uint32_t run = incl - mine, total = 0;
-    for (uint32_t q = 0; q < kFinThreads / 64; ++q) {
-        if (q < wv) run += wtot[q];
-        total += wtot[q];
-    }
-    for (uint32_t q = 0; q < rs; ++q) {
-        const uint32_t r = t * rs + q;
-        if (r < nr) {
-            pre[r] = run;
-            run += ((cell[r] >> 16) + 3u) >> 2;    // the clamped count's pieces
-        }
-    }
-    if (t == 0) pre[nr] = total;
     __syncthreads();
     {
-        // Live results: piece c (up to 4 results, 16 bytes: host within its
-        // subgroup << 16 | distance) belongs to the run r with pre[r] <= c <
-        // pre[r + 1]; each is counted into its host's bin with an LDS atomic.
-        // Bin k (inactive) is not counted: it is g minus the others, filled
-        // in below.
-        // kFinB pieces per thread at a time: their runs found, their loads
-        // issued together, then their counts.
-        for (uint32_t c0 = t; c0 < total; c0 += kFinB * kFinThreads) {
-            uint4 w4[kFinB];
-            uint32_t nv[kFinB], hrow[kFinB];
+        // Live results (host within its subgroup << 16 | distance) of run r
+        // (slice r mod n_slices of subgroup s0 + r / n_slices): the first
+        // four in the run's 16-byte cell of `heads`, any more in the run's
+        // own result slots.  Each is counted into its host's bin with an LDS
+        // atomic; bin k (inactive) is not counted: it is g minus the others,
+        // filled in below.  (A live count never exceeds the run's entries;
+        // the clamp keeps every read inside them whatever the table holds.)
+        const uint4 *heads4 = reinterpret_cast<const uint4 *>(heads);
+        for (uint32_t r = t; r < nr; r += kFinThreads) {
+            const uint32_t sg = r / ns, b = r - sg * ns;
+            const uint32_t *trow = table + (size_t)(s0 + sg) * (ns + 1);
+            const uint32_t c = trow[b], start = c & 0xFFFFu;
+            const uint32_t cnt = min(c >> 16, 4u * ((trow[b + 1] & 0xFFFFu) - start));
+            if (cnt == 0) continue;
+            const uint32_t hrow = sg * PG.hosts;
+            const uint4 w4 = heads4[(size_t)(s0 + sg) * ns + b];
 #pragma unroll
-            for (uint32_t b = 0; b < kFinB; ++b) {
-                const uint32_t c = c0 + b * kFinThreads;
-                nv[b] = 0;
-                hrow[b] = 0;
-                w4[b] = make_uint4(0, 0, 0, 0);
-                if (c < total) {
-                    uint32_t lo = 0, hi = nr;        // largest r with pre[r] <= c
-                    while (hi - lo > 1) {
-                        const uint32_t mid = (lo + hi) >> 1;
-                        if (pre[mid] <= c) lo = mid; else hi = mid;
-                    }
-                    const uint32_t k4 = c - pre[lo];
-                    const uint32_t cb = cell[lo];
-                    const uint32_t sg = lo / ns;
-                    nv[b] = min(4u, (cb >> 16) - 4u * k4);
-                    hrow[b] = sg * PG.hosts;
-                    w4[b] = reinterpret_cast<const uint4 *>(hits + (size_t)(s0 + sg) * PG.region)[(cb & 0xFFFFu) + k4];
-                }
+            for (uint32_t m = 0; m < 4; ++m) {
+                if (m >= cnt) break;
+                const uint32_t v = comp4(w4, m), d = v & 0xFFFFu;
+                if (d < G.k) atomicAdd(&hist[(hrow + (v >> 16)) * rowp + (d >> 1)], 1u << ((d & 1u) << 4));
             }
-#pragma unroll
-            for (uint32_t b = 0; b < kFinB; ++b)
-#pragma unroll
-                for (uint32_t m = 0; m < 4; ++m) {
-                    if (m >= nv[b]) break;
-                    const uint32_t r = comp4(w4[b], m), d = r & 0xFFFFu;
-                    if (d >= G.k) continue;
-                    atomicAdd(&hist[(hrow[b] + (r >> 16)) * rowp + (d >> 1)], 1u << ((d & 1u) << 4));
-                }
+            const uint32_t *more = hits + (size_t)(s0 + sg) * PG.region + 4u * start;
+            for (uint32_t i = 4; i < cnt; ++i) {
+                const uint32_t v = more[i - 4u], d = v & 0xFFFFu;
+                if (d < G.k) atomicAdd(&hist[(hrow + (v >> 16)) * rowp + (d >> 1)], 1u << ((d & 1u) << 4));
+            }
         }
     }
     __syncthreads();
