@@ -493,6 +493,9 @@ __device__ __forceinline__ void learned16(const Geo &G, float occupancy, const u
 {
     const int l = threadIdx.x & 63, q = l >> 4, c = l & 15;
     const float fg = (float)G.g;
+    // x / g as a product when g is a power of two (then exactly equal)
+    const bool g_pow2 = (G.g & (G.g - 1u)) == 0u;
+    const float inv_g = 1.0f / fg;
     // Row m (host m) is built by the whole wavefront, lane f = feature f, so
     // one ballot per row says whether the host is outside the envelope.
     uint32_t outside = mlp::env_geometry_off(P, G.k, G.g, G.c, G.wb) ? 0xFFFFu : 0u;
@@ -502,9 +505,10 @@ __device__ __forceinline__ void learned16(const Geo &G, float occupancy, const u
         float x = 0.f;
         if ((uint32_t)m < n16) {
             if (f < (int)G.k)
-                x = (float)hist_bin(rw + m * rowp, f) / fg;
+                x = (float)hist_bin(rw + m * rowp, f);
             else if (f == (int)G.k)
-                x = (float)live16[m] / fg;
+                x = (float)live16[m];
+            if (f <= (int)G.k) x = g_pow2 ? x * inv_g : x / fg;
             else if (f == (int)G.k + 1)
                 x = occupancy;
             else if (f == (int)G.k + 2)
@@ -638,8 +642,10 @@ __global__ void __launch_bounds__(kFinThreads, 5) k_run_finalize(Geo G, PartGeo 
     } else {
         // Learned estimate, in groups of 64 hosts (16 per wavefront): the
         // closed form for window k, then the network fed from the LDS rows.
+        // One 16-row staging tile per wavefront holds its features and then
+        // its first layer's activations: the layer's inputs are in registers
+        // (its products depend on them) before its outputs are written.
         __shared__ __attribute__((aligned(16))) uint16_t xs_all[kFinThreads / 64][16 * mlp::LDS_STRIDE];
-        __shared__ __attribute__((aligned(16))) uint16_t a1_all[kFinThreads / 64][16 * mlp::LDS_STRIDE];
         __shared__ float cf_s[kFinThreads / 4];
         __shared__ uint32_t live_s[kFinThreads / 4];
         const uint64_t active_pool = pool_active(st, G.k);
@@ -674,7 +680,7 @@ __global__ void __launch_bounds__(kFinThreads, 5) k_run_finalize(Geo G, PartGeo 
             const mlp::Packed *Pg = P;
             asm volatile("" : "+s"(Pg));
             learned16(G, occupancy, hist + m0 * rowp, rowp, n16, cf_s + 16 * w, live_s + 16 * w, xs_all[w],
-                      a1_all[w], Pg, est + h0 + m0);
+                      xs_all[w], Pg, est + h0 + m0);
             __syncthreads();
         }
     }
