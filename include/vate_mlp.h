@@ -54,8 +54,8 @@ int vate_mlp_pack(const float *theta_dev, void *weights_dev, void *stream);
  *   - for every host, when the sketch's k, g, log2_pool or width differs
  *     from the envelope's (the features then mean something else), and
  *   - for a host any of whose features lies outside [lo[f], hi[f]],
- * and count those hosts (plus hosts whose network output is not finite) in a
- * device counter kept with the weights. */
+ * and count those hosts (plus hosts whose network output is not finite) in
+ * device counters kept with the weights (vate_mlp_fallbacks sums them). */
 typedef struct vate_mlp_envelope {
     uint32_t k, g, log2_pool, width;
     float lo[VATE_MLP_FEATURES];
@@ -63,12 +63,12 @@ typedef struct vate_mlp_envelope {
 } vate_mlp_envelope;
 
 /* Set (env non-NULL) or clear (env NULL) the envelope of packed weights and
- * zero their fallback counter.  Synchronises `stream`, then copies; env is
+ * zero their fallback counters.  Synchronises `stream`, then copies; env is
  * read during the call only.  Errors: VATE_E_INVAL, VATE_E_DEVICE. */
 int vate_mlp_set_envelope(void *weights_dev, const vate_mlp_envelope *env, void *stream);
 
 /* Hosts given the closed form by the envelope (or a non-finite network
- * output) since the counter was last zeroed; reset != 0 zeroes it.
+ * output) since the counters were last zeroed; reset != 0 zeroes them.
  * Synchronises `stream`.  Errors: VATE_E_INVAL, VATE_E_DEVICE. */
 int vate_mlp_fallbacks(const void *weights_dev, uint64_t *count, int reset, void *stream);
 

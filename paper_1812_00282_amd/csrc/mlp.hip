@@ -49,8 +49,8 @@ __global__ void k_pack(const float *__restrict__ theta, Packed *__restrict__ P)
         if (threadIdx.x == 0) {
             P->b3 = theta[OFF_B3];
             P->env.magic = 0;         // packing switches the envelope off
-            P->env.fallbacks = 0;
         }
+        for (int i = threadIdx.x; i < kFallbackSlots; i += blockDim.x) P->fallbacks[i] = 0;
     }
 }
 
@@ -326,8 +326,10 @@ int vate_mlp_set_envelope(void *weights_dev, const vate_mlp_envelope *env, void 
         for (int f = 0; f < F; ++f) e.lo[f] = env->lo[f], e.hi[f] = env->hi[f];
     }
     Packed *P = static_cast<Packed *>(weights_dev);
+    const unsigned long long zero[kFallbackSlots] = {};
     hipError_t err = hipStreamSynchronize(static_cast<hipStream_t>(stream));
     if (err == hipSuccess) err = hipMemcpy(&P->env, &e, sizeof(Envelope), hipMemcpyHostToDevice);
+    if (err == hipSuccess) err = hipMemcpy(P->fallbacks, zero, sizeof(zero), hipMemcpyHostToDevice);
     return err == hipSuccess ? VATE_OK : VATE_E_DEVICE;
 }
 
@@ -335,16 +337,17 @@ int vate_mlp_fallbacks(const void *weights_dev, uint64_t *count, int reset, void
 {
     if (!weights_dev || !count || (reinterpret_cast<uintptr_t>(weights_dev) & 255u)) return VATE_E_INVAL;
     const Packed *P = static_cast<const Packed *>(weights_dev);
-    unsigned long long c = 0;
+    unsigned long long c[kFallbackSlots] = {};
     hipError_t err = hipStreamSynchronize(static_cast<hipStream_t>(stream));
-    if (err == hipSuccess) err = hipMemcpy(&c, &P->env.fallbacks, sizeof(c), hipMemcpyDeviceToHost);
+    if (err == hipSuccess) err = hipMemcpy(c, P->fallbacks, sizeof(c), hipMemcpyDeviceToHost);
     if (err == hipSuccess && reset) {
-        const unsigned long long zero = 0;
-        err = hipMemcpy(const_cast<unsigned long long *>(&P->env.fallbacks), &zero, sizeof(zero),
-                        hipMemcpyHostToDevice);
+        const unsigned long long zero[kFallbackSlots] = {};
+        err = hipMemcpy(const_cast<unsigned long long *>(P->fallbacks), zero, sizeof(zero), hipMemcpyHostToDevice);
     }
     if (err != hipSuccess) return VATE_E_DEVICE;
-    *count = c;
+    uint64_t sum = 0;
+    for (int i = 0; i < kFallbackSlots; ++i) sum += c[i];
+    *count = sum;
     return VATE_OK;
 }
 

@@ -31,16 +31,21 @@ constexpr int OFF_B3 = OFF_W3 + HD;
 static_assert(OFF_B3 + 1 == VATE_MLP_PARAMS, "parameter count");
 
 // The network's training envelope (vate_mlp_envelope) as kept with the
-// packed weights, plus the count of hosts it sent to the closed form.
+// packed weights.
 constexpr uint32_t kEnvMagic = 0x31564E45u;   // set by vate_mlp_set_envelope; anything else: no envelope
 struct Envelope {
     uint32_t magic;
     uint32_t k, g, log2_pool, width;
     uint32_t pad[3];
-    unsigned long long fallbacks;
-    unsigned long long pad2;
+    unsigned long long pad1[2];
     float lo[F], hi[F];
 };
+
+// Hosts the envelope sent to the closed form, counted in kFallbackSlots
+// counters (a workgroup adds its count to slot blockIdx mod kFallbackSlots,
+// so that no counter takes an atomic from every workgroup); the reader sums
+// them.
+constexpr int kFallbackSlots = 16;
 
 // Packed inference weights (bytes).
 struct Packed {
@@ -50,7 +55,8 @@ struct Packed {
     float b1[HD], b2[HD], w3[HD], b3;
     float pad[63];
     Envelope env;
-    float pad3[52];
+    unsigned long long fallbacks[kFallbackSlots];
+    float pad3[20];
 };
 static_assert(sizeof(Packed) == VATE_MLP_WEIGHT_BYTES, "packed weight size");
 
@@ -81,10 +87,10 @@ __device__ __forceinline__ bool env_outside(const EnvRange &r, uint16_t xb)
     return !(x >= r.lo && x <= r.hi);
 }
 
-// Adds n hosts to the envelope's fallback count (one lane per call).
+// Adds a workgroup's n fallback hosts to its slot (one lane per workgroup).
 __device__ __forceinline__ void env_count(const Packed *P, uint32_t n)
 {
-    if (n) atomicAdd(&const_cast<Packed *>(P)->env.fallbacks, (unsigned long long)n);
+    if (n) atomicAdd(&const_cast<Packed *>(P)->fallbacks[blockIdx.x % kFallbackSlots], (unsigned long long)n);
 }
 
 // FP32 -> BF16 bits, round to nearest even (finite inputs).

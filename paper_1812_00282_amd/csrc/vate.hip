@@ -742,6 +742,9 @@ __global__ void __launch_bounds__(256) k_estimate_learned(Geo G, const uint8_t *
     __syncthreads();
     const bool geo_off = mlp::env_geometry_off(P, G.k, G.g, G.c, G.wb);
     const mlp::EnvRange rng = mlp::env_range(P, (int)lane);   // this lane's feature in every row
+    __shared__ uint32_t fell_wg;      // the workgroup's fallback hosts (one counter atomic per workgroup)
+    if (threadIdx.x == 0) fell_wg = 0;
+    uint32_t fell_wave = 0;
     for (int t = 0; t < 4; ++t) {
         // features of hosts 16t .. 16t+15 of this wavefront (row m = host - 16t);
         // lane f builds feature f of a row, so one ballot per row says whether
@@ -779,10 +782,12 @@ __global__ void __launch_bounds__(256) k_estimate_learned(Geo G, const uint8_t *
                 est_out[hg] = fell ? cf_all[wave][host] : e;
             }
         }
-        const uint64_t fb = __ballot(fell);
-        if (lane == 0) mlp::env_count(P, (uint32_t)__popcll(fb));
+        fell_wave += (uint32_t)__popcll(__ballot(fell));
         __syncthreads();
     }
+    if (lane == 0 && fell_wave) atomicAdd(&fell_wg, fell_wave);
+    __syncthreads();
+    if (threadIdx.x == 0) mlp::env_count(P, fell_wg);
 }
 
 #include "vate_part.h"

@@ -487,7 +487,8 @@ __device__ __forceinline__ uint32_t hist_bin(const uint32_t *row, uint32_t d)
 // and closed forms (LDS, 16 each), the network on the matrix cores, exp of
 // its output (the closed form where that is not finite) to est[0, n16).
 // Every wavefront of the workgroup calls it (the network has a barrier).
-__device__ __forceinline__ void learned16(const Geo &G, float occupancy, const uint32_t *rw, uint32_t rowp,
+// Returns the hosts given the closed form (the same in every lane).
+__device__ __forceinline__ uint32_t learned16(const Geo &G, float occupancy, const uint32_t *rw, uint32_t rowp,
                                           uint32_t n16, const float *cf16, const uint32_t *live16, uint16_t *xs,
                                           uint16_t *a1, const mlp::Packed *__restrict__ P, float *__restrict__ est)
 {
@@ -534,8 +535,7 @@ __device__ __forceinline__ void learned16(const Geo &G, float occupancy, const u
             est[m] = fell ? cf16[m] : ex;
         }
     }
-    const uint64_t fb = __ballot(fell);
-    if (l == 0) mlp::env_count(P, (uint32_t)__popcll(fb));
+    return (uint32_t)__popcll(__ballot(fell));
 }
 
 // At least 5 wavefronts per SIMD: the network's registers would otherwise
@@ -651,6 +651,9 @@ __global__ void __launch_bounds__(kFinThreads, 5) k_run_finalize(Geo G, PartGeo 
         const uint64_t active_pool = pool_active(st, G.k);
         const float occupancy = (float)active_pool / (float)G.N;
         const uint32_t w = t >> 6;
+        __shared__ uint32_t fell_wg;      // the workgroup's fallback hosts (one counter atomic per workgroup)
+        if (t == 0) fell_wg = 0;
+        uint32_t fell_wave = 0;
         for (uint32_t base = 0; base < nh; base += kFinThreads / 4) {
             {   // live count and closed form of host base + t / 4, four threads a host
                 const uint32_t hh = t >> 2, qq = t & 3u;
@@ -679,10 +682,13 @@ __global__ void __launch_bounds__(kFinThreads, 5) k_run_finalize(Geo G, PartGeo 
             // are used rather than hoisted out of the loop into registers.
             const mlp::Packed *Pg = P;
             asm volatile("" : "+s"(Pg));
-            learned16(G, occupancy, hist + m0 * rowp, rowp, n16, cf_s + 16 * w, live_s + 16 * w, xs_all[w],
-                      xs_all[w], Pg, est + h0 + m0);
+            fell_wave += learned16(G, occupancy, hist + m0 * rowp, rowp, n16, cf_s + 16 * w, live_s + 16 * w,
+                                   xs_all[w], xs_all[w], Pg, est + h0 + m0);
             __syncthreads();
         }
+        if ((t & 63u) == 0 && fell_wave) atomicAdd(&fell_wg, fell_wave);
+        __syncthreads();
+        if (t == 0) mlp::env_count(P, fell_wg);
     }
 }
 
