@@ -288,3 +288,22 @@ def test_envelope_per_host_ranges():
         assert torch.equal(got[out], cf[out]), part
         assert torch.equal(got[~out], free[~out]), part
         assert L.fallbacks(guarded, reset=True) == int(outside.sum()), part
+
+
+def test_envelope_counts_across_many_workgroups():
+    """Every host of a 60,000-host estimate falls back (an envelope of another
+    pool size): the fallback counters, kept in slots per workgroup, sum to the
+    host count on both paths, and every estimate is the closed form."""
+    from paper_1812_00282_amd import train as T
+    cfg, gpu, ref, _ = _k60_sketch(log2_pool=21, n_hosts=3000, slices=8, seed=62)
+    hosts = np.random.default_rng(63).choice(2**32, size=60_000, replace=False).astype(np.uint32)
+    env = {"k": cfg.k, "g": cfg.g, "log2_pool": cfg.log2_pool + 1, "width": cfg.width,
+           "lo": np.full(64, -1e30, np.float32), "hi": np.full(64, 1e30, np.float32)}
+    w = L.set_envelope(L.pack(T.load(), L.new_weights()), env)
+    assert L.fallbacks(w) == 0
+    for part in (False, True):
+        learn, cf = L.estimate_learned(gpu, hosts, w, partitioned=part)
+        torch.cuda.synchronize()
+        assert torch.equal(learn, cf), part
+        assert L.fallbacks(w, reset=True) == hosts.size, part
+    assert L.fallbacks(w) == 0
