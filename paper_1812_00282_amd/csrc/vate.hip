@@ -452,67 +452,121 @@ __global__ void __launch_bounds__(256) k_census(Geo G, const uint4 *__restrict__
 // k_census8: the census of byte counters with k <= kCensus8Bins.  In steady
 // state only a few per cent of the chunks hold an active AT, but nearly every
 // wavefront has one among its 64, so a per-lane test would run the packed
-// activity test on all of them.  Here each wavefront first writes the zero
-// bits of its all-inactive chunks and stages the others in LDS (compacted,
-// in lane order), then its lanes take the staged chunks one each.
+// activity test on all of them.  Here each wavefront stages the busy chunks
+// of a round in LDS (compacted, in lane order), its lanes test the staged
+// chunks one each and leave each chunk's bits in its staging slot, and the
+// chunk's own lane picks them up; all-inactive chunks have zero bits.
+//
+// The rounds in which every lane's chunks lie inside the pool are software
+// pipelined: a round's loads are issued before the previous round is tested,
+// and its bitmap stores (a fixed number per lane) after, so the wait for the
+// loads never covers a store that is still in flight.  The remaining rounds
+// (at most one per thread) are guarded.
 constexpr uint32_t kCensus8Bins = 256;
 constexpr int kCensus8U = 4;   // chunks per lane and round
+
+struct Census8Lds {
+    uint32_t hist[kCensus8Bins];
+    uint4 v[4][64 * kCensus8U];       // staged chunks of each wavefront
+    uint16_t c[4][64 * kCensus8U];    // staged chunk's (u * 64 + lane), then its bits
+};
+
+// One round of U chunks per lane (chunk u of this lane is c0 + u * stride):
+// bits[u] = the activity bits of chunk u.
+__device__ __forceinline__ void census8_round(const Geo &G, const uint4 (&v)[kCensus8U], uint64_t c0, uint64_t stride,
+                                              uint32_t bact0, uint32_t pat, Census8Lds &L, uint32_t (&bits)[kCensus8U],
+                                              unsigned long long *census)
+{
+    constexpr int U = kCensus8U;
+    const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+    uint32_t n = 0;          // staged chunks of this wavefront (uniform)
+    uint32_t pos[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const bool busy = v[u].x != pat || v[u].y != pat || v[u].z != pat || v[u].w != pat;
+        const uint64_t m = __ballot(busy);
+        pos[u] = busy ? n + (uint32_t)__popcll(m & ((1ull << lane) - 1ull)) : ~0u;
+        if (busy) {
+            L.v[wv][pos[u]] = v[u];
+            L.c[wv][pos[u]] = (uint16_t)(u * 64 + lane);
+        }
+        n += (uint32_t)__popcll(m);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const uint64_t wbase = c0 - lane;
+    for (uint32_t i = lane; i < n; i += 64) {
+        const uint32_t code = L.c[wv][i];
+        const uint64_t ch = wbase + (code & 63u) + (uint64_t)(code >> 6) * stride;
+        L.c[wv][i] = (uint16_t)census_chunk_fast<8>(G, L.v[wv][i], ch, bact0, pat, L.hist, census);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int u = 0; u < U; ++u) bits[u] = pos[u] != ~0u ? (uint32_t)L.c[wv][pos[u]] : 0u;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 __global__ void __launch_bounds__(256) k_census8(Geo G, const uint4 *__restrict__ pool4, uint64_t nchunks,
                                                  DevState *__restrict__ st, uint8_t *__restrict__ bitmap,
                                                  unsigned long long *__restrict__ copies)
 {
     constexpr int U = kCensus8U;
-    __shared__ uint32_t hist[kCensus8Bins];
-    __shared__ uint4 stage_v[4][64 * U];
-    __shared__ uint8_t stage_c[4][64 * U];     // u * 64 + lane of the staged chunk
-    for (uint32_t d = threadIdx.x; d < G.k; d += blockDim.x) hist[d] = 0;
+    __shared__ Census8Lds L;
+    for (uint32_t d = threadIdx.x; d < G.k; d += blockDim.x) L.hist[d] = 0;
     __syncthreads();
     const uint32_t bact0 = st->bact0;
     const uint32_t pat = replicate<8>(inactive_value(G));
-    const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t c0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c0 - lane < nchunks; c0 += U * stride) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x, step = U * stride;
+    uint16_t *bm16 = reinterpret_cast<uint16_t *>(bitmap);
+    uint64_t c0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t bits[U];
+    const uint64_t full = nchunks / step;      // rounds with every chunk inside the pool
+    if (full > 0) {
+        uint4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = pool4[c0 + u * stride];
+        // The first round's chunks are waited for here, so that the loop
+        // entry leaves no load in flight that the loop head would wait for
+        // (a wait there would also cover the previous round's stores).
+#pragma unroll
+        for (int u = 0; u < U; ++u) asm volatile("" ::"v"(v[u].x), "v"(v[u].y), "v"(v[u].z), "v"(v[u].w));
+        for (uint64_t r = 0; r < full; ++r, c0 += step) {
+            // the next round's chunks (the last round reloads its own)
+            const uint64_t nx = r + 1 < full ? c0 + step : c0;
+            uint4 w[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) w[u] = pool4[nx + u * stride];
+            census8_round(G, v, c0, stride, bact0, pat, L, bits, census_of(st));
+#pragma unroll
+            for (int u = 0; u < U; ++u) bm16[c0 + u * stride] = (uint16_t)bits[u];
+#pragma unroll
+            for (int u = 0; u < U; ++u) v[u] = w[u];
+        }
+    }
+    for (; c0 - lane < nchunks; c0 += step) {
         uint4 v[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const uint64_t ch = c0 + u * stride;
             v[u] = ch < nchunks ? pool4[ch] : make_uint4(pat, pat, pat, pat);
         }
-        uint32_t n = 0;      // staged chunks of this wavefront (uniform)
+        census8_round(G, v, c0, stride, bact0, pat, L, bits, census_of(st));
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const uint64_t ch = c0 + u * stride;
-            const bool busy = v[u].x != pat || v[u].y != pat || v[u].z != pat || v[u].w != pat;
-            const uint64_t m = __ballot(busy);
-            if (busy) {
-                const uint32_t pos = n + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-                stage_v[wv][pos] = v[u];
-                stage_c[wv][pos] = (uint8_t)(u * 64 + lane);
-            } else if (ch < nchunks) {
-                store_bits<8>(bitmap, ch, 0u);
-            }
-            n += (uint32_t)__popcll(m);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const uint64_t wbase = c0 - lane;
-        for (uint32_t i = lane; i < n; i += 64) {
-            const uint32_t code = stage_c[wv][i];
-            const uint64_t ch = wbase + (code & 63u) + (uint64_t)(code >> 6) * stride;
-            store_bits<8>(bitmap, ch, census_chunk_fast<8>(G, stage_v[wv][i], ch, bact0, pat, hist, census_of(st)));
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int u = 0; u < U; ++u)
+            if (c0 + u * stride < nchunks) bm16[c0 + u * stride] = (uint16_t)bits[u];
     }
     __syncthreads();
     // Flush into copy blockIdx mod kCensusCopies (k_census_fold adds the
     // copies to the census).
     unsigned long long *mine = copies + (size_t)(blockIdx.x % kCensusCopies) * G.k;
     for (uint32_t d = threadIdx.x; d < G.k; d += blockDim.x)
-        if (hist[d]) atomicAdd(&mine[d], (unsigned long long)hist[d]);
+        if (L.hist[d]) atomicAdd(&mine[d], (unsigned long long)L.hist[d]);
 }
 
 __global__ void __launch_bounds__(256) k_census_fold(Geo G, DevState *__restrict__ st,

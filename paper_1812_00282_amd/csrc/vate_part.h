@@ -129,7 +129,28 @@ __global__ void __launch_bounds__(kRunThreads) k_run_scatter(Geo G, PartGeo PG, 
         // mix (shift = 32 - c is at most 31).  Each VAT's pid stays in a
         // register until it is placed.
         uint32_t pid[kRunPerThread];
-        if (PG.dr == 0) {
+        // When g is a multiple of 64 (and divides the workgroup size), the 64
+        // lanes of a wavefront hash VATs of one host in every round: its key
+        // is one broadcast LDS read and the round's bound a scalar test.  All
+        // hashes come first (the key reads then wait for no LDS atomic), then
+        // the counts.  Keys past the subgroup's hosts (the LDS after the keys
+        // holds the sort slots) give pids that are never counted or placed.
+        const bool wave_host = PG.dr == 0 && (G.g & 63u) == 0;
+        const uint32_t host_w = __builtin_amdgcn_readfirstlane(host_t);
+        if (wave_host) {
+            const uint32_t ik = i_t * kPhi;
+            const uint32_t *kw = keys + host_w;
+            if (PG.dq == 1) {
+#pragma unroll
+                for (uint32_t j = 0; j < kRunPerThread; ++j) pid[j] = mix(kw[j] ^ ik) >> G.shift;
+            } else {
+#pragma unroll
+                for (uint32_t j = 0; j < kRunPerThread; ++j) pid[j] = mix(kw[j * PG.dq] ^ ik) >> G.shift;
+            }
+#pragma unroll
+            for (uint32_t j = 0; j < kRunPerThread; ++j)
+                if (host_w + j * PG.dq < nh) atomicAdd(&cnt[pid[j] >> sl], 1u);
+        } else if (PG.dr == 0) {
             const uint32_t ik = i_t * kPhi;
 #pragma unroll
             for (uint32_t j = 0; j < kRunPerThread; ++j) {
@@ -156,6 +177,11 @@ __global__ void __launch_bounds__(kRunThreads) k_run_scatter(Geo G, PartGeo PG, 
             }
         }
         __syncthreads();
+        // The keys are not read again in this subgroup: the next one's take
+        // their place now, while no store of this workgroup is in flight (a
+        // wait for the host id load after the copy-out below would also wait
+        // for every store of the copy-out).
+        if (t < nh_next) keys[t] = host_key(G, aip_next);
 
         // Exclusive scan of the padded slice counts; thread t owns slices
         // [t ps, (t+1) ps).  Run starts become the cursors, padding slots
@@ -196,7 +222,16 @@ __global__ void __launch_bounds__(kRunThreads) k_run_scatter(Geo G, PartGeo PG, 
 
         // Placement: each VAT's entry (host within subgroup, AT within slice)
         // at its slice's cursor.
-        if (PG.dr == 0) {
+        if (wave_host) {
+#pragma unroll
+            for (uint32_t j = 0; j < kRunPerThread; ++j) {
+                const uint32_t host = host_w + j * PG.dq;
+                if (host < nh) {
+                    const uint32_t slot = atomicAdd(&cnt[pid[j] >> sl], 1u);
+                    sorted[slot] = (host << (sl + 1)) | (pid[j] & mask);
+                }
+            }
+        } else if (PG.dr == 0) {
 #pragma unroll
             for (uint32_t j = 0; j < kRunPerThread; ++j)
                 if (t + j * kRunThreads < nv) {
@@ -221,10 +256,9 @@ __global__ void __launch_bounds__(kRunThreads) k_run_scatter(Geo G, PartGeo PG, 
         // Copy out as one coalesced stream.
         uint4 *out = reinterpret_cast<uint4 *>(entries + (size_t)s * PG.region);
         for (uint32_t q = t; q < total / 4; q += kRunThreads) out[q] = reinterpret_cast<const uint4 *>(sorted)[q];
-        // Ready the next subgroup: the copy above reads only the sorted
-        // entries, and the keys are not read after the placement.
+        // Ready the next subgroup's counters: the copy above reads only the
+        // sorted entries.
         for (uint32_t q = t; q < nsp; q += kRunThreads) cnt[q] = 0;
-        if (t < nh_next) keys[t] = host_key(G, aip_next);
         __syncthreads();
     }
 }
