@@ -62,7 +62,7 @@ typedef struct vate_params {
                             bits (Sec. 3), so 2^width >= 2k+1.  4, 8 and 16 use
                             nibble/byte/short containers; any other width packs
                             the ATs exactly (e.g. 7 bits at k = 60, 10 at
-                            k = 300) - the batched calls take 4/8/16 only */
+                            k = 300), in the single-sketch and batched calls */
     uint32_t k;          /* longest window, in slices (Sec. 1); k >= 1 */
     uint32_t g;          /* VATs per host (Sec. 4.1); 1 <= g <= 65535 */
     uint32_t partition;  /* 0: Eq. 9-10 blocks (Fig. 4: 2k-1 blocks of

@@ -31,7 +31,8 @@ typedef struct vate_batch vate_batch;
 /* Launch shape of each batched phase. */
 typedef struct vate_batch_tune {
     uint32_t ingest_tile;     /* packets per claimed tile, multiple of 512 */
-    uint32_t census_tile;     /* 16-byte pool chunks per tile, multiple of 256 */
+    uint32_t census_tile;     /* 16-byte pool chunks per tile (exact widths: groups
+                                 of 32 counters), multiple of 256 */
     uint32_t estimate_block;  /* threads per estimate workgroup (64, 128 or 256) */
     uint32_t grid_preserve, grid_ingest, grid_census, grid_estimate;  /* workgroups */
     uint32_t estimate_lanes;  /* lanes sharing one host's g gathers (1, 4 or 16);

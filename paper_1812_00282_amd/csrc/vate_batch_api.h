@@ -111,8 +111,6 @@ int vate_batch_create(vate_sketch *const *sketches, uint32_t n, void *batch_dev,
         return VATE_E_INVAL;
     for (uint32_t i = 0; i < n; ++i) {
         if (!sketches[i] || sketches[i]->dead) return VATE_E_INVAL;
-        const uint32_t w = sketches[i]->p.width;
-        if (w != 4 && w != 8 && w != 16) return VATE_E_UNSUPPORTED;   // batched kernels use 4/8/16-bit containers
         for (uint32_t j = 0; j < i; ++j)
             if (sketches[j] == sketches[i]) return VATE_E_INVAL;
     }
@@ -137,9 +135,10 @@ int vate_batch_create(vate_sketch *const *sketches, uint32_t n, void *batch_dev,
         it.pool = s->pool;
         it.st = s->st;
         it.bitmap = s->bitmap;
-        it.nchunks = s->pool_bytes / 16;
-        it.max_block_chunks = s->max_block_chunks;
-        it.width = s->p.width;
+        const bool exact = s->p.width != 4 && s->p.width != 8 && s->p.width != 16;
+        it.nchunks = exact ? s->G.N / 32 : s->pool_bytes / 16;   // groups of 32 counters / 16-byte chunks
+        it.max_block_chunks = s->max_block_chunks;               // in the same units
+        it.width = exact ? 0u : s->p.width;
         it.kprime = s->p.k;
     }
     hipError_t e = hipMemcpy(b->items, b->host_items, sizeof(BatchItem) * n, hipMemcpyHostToDevice);

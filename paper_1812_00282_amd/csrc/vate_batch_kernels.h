@@ -22,9 +22,9 @@ struct BatchItem {
     float *est;
     uint32_t *live;
     uint64_t pairs_cap;          // capacity of the pair buffer (packets)
-    uint64_t nchunks;            // 16-byte pool chunks
-    uint64_t max_block_chunks;   // chunks one due block can overlap
-    uint32_t width, n_hosts, kprime, pad;
+    uint64_t nchunks;            // streaming units: 16-byte pool chunks (exact widths: 32-counter groups)
+    uint64_t max_block_chunks;   // units one due block can overlap
+    uint32_t width, n_hosts, kprime, pad;   // width 0: an exact-width pool (G.wb bits per counter)
 };
 
 // Launch shape of each phase (chosen by the autotuner).
@@ -125,16 +125,19 @@ __global__ void __launch_bounds__(256) k_batch_preserve(const BatchItem *__restr
         const BatchItem &it = items[s];
         const uint64_t j = (tile - tab->prefix[PH_PRESERVE][s]) * 256 + threadIdx.x;
         uint4 *pool4 = reinterpret_cast<uint4 *>(it.pool);
+        uint32_t *pool32 = reinterpret_cast<uint32_t *>(it.pool);
         const uint32_t bact0 = it.st->bact0;
         if (it.G.dr) {
             if (j < it.nchunks) {
-                if (it.width == 4) dr_maintain_chunk<4>(it.G, pool4, j);
+                if (it.width == 0) dr_maintain_group_x(it.G, pool32, j);
+                else if (it.width == 4) dr_maintain_chunk<4>(it.G, pool4, j);
                 else if (it.width == 8) dr_maintain_chunk<8>(it.G, pool4, j);
                 else dr_maintain_chunk<16>(it.G, pool4, j);
             }
             continue;
         }
-        if (it.width == 4) preserve_chunk<4>(it.G, pool4, bact0, j, it.max_block_chunks);
+        if (it.width == 0) preserve_group_x(it.G, pool32, bact0, j, it.max_block_chunks);
+        else if (it.width == 4) preserve_chunk<4>(it.G, pool4, bact0, j, it.max_block_chunks);
         else if (it.width == 8) preserve_chunk<8>(it.G, pool4, bact0, j, it.max_block_chunks);
         else preserve_chunk<16>(it.G, pool4, bact0, j, it.max_block_chunks);
     }
@@ -170,7 +173,8 @@ __global__ void __launch_bounds__(256) k_batch_ingest(const BatchItem *__restric
         const BatchItem &it = items[s];
         const uint64_t p0 = (tile - tab->prefix[PH_INGEST][s]) * tune.ingest_tile;
         const uint64_t p1 = min(p0 + tune.ingest_tile, min((uint64_t)n_pairs[s], it.pairs_cap));
-        if (it.width == 4) batch_ingest_tile<4>(it, p0, p1);
+        if (it.width == 0) batch_ingest_tile<0>(it, p0, p1);
+        else if (it.width == 4) batch_ingest_tile<4>(it, p0, p1);
         else if (it.width == 8) batch_ingest_tile<8>(it, p0, p1);
         else batch_ingest_tile<16>(it, p0, p1);
     }
@@ -196,6 +200,16 @@ __device__ __forceinline__ void batch_census_tile(const BatchItem &it, uint64_t 
             if (ch < c1) store_bits<W>(it.bitmap, ch, census_chunk_fast<W>(it.G, v[u], ch, bact0, pat, h, census_of(it.st)));
         }
     }
+}
+
+// Exact widths: groups [c0, c1) of 32 counters.
+__device__ __forceinline__ void batch_census_groups(const BatchItem &it, uint64_t c0, uint64_t c1, uint32_t *hist)
+{
+    const uint32_t bact0 = it.st->bact0;
+    const uint32_t *pool32 = reinterpret_cast<const uint32_t *>(it.pool);
+    uint32_t *h = it.G.k <= kBatchCensusBins ? hist : nullptr;
+    for (uint64_t gi = c0 + threadIdx.x; gi < c1; gi += blockDim.x)
+        census_group_x(it.G, pool32, gi, bact0, h, census_of(it.st), it.bitmap);
 }
 
 // The LDS histogram belongs to one sketch at a time: it is flushed into that
@@ -224,7 +238,8 @@ __global__ void __launch_bounds__(256) k_batch_census(const BatchItem *__restric
         const BatchItem &it = items[s];
         const uint64_t c0 = (tile - tab->prefix[PH_CENSUS][s]) * tune.census_tile;
         const uint64_t c1 = min(c0 + tune.census_tile, it.nchunks);
-        if (it.width == 4) batch_census_tile<4, U>(it, c0, c1, hist);
+        if (it.width == 0) batch_census_groups(it, c0, c1, hist);
+        else if (it.width == 4) batch_census_tile<4, U>(it, c0, c1, hist);
         else if (it.width == 8) batch_census_tile<8, U>(it, c0, c1, hist);
         else batch_census_tile<16, U>(it, c0, c1, hist);
     }
@@ -279,7 +294,8 @@ __global__ void __launch_bounds__(256) k_batch_estimate(const BatchItem *__restr
         const bool valid = h < it.n_hosts;
         const uint32_t key = host_key(it.G, valid ? it.hosts[h] : 0u);
         uint32_t live;
-        if (it.width == 4) live = batch_host_live<4, L>(it, key, valid, bact0, sub);
+        if (it.width == 0) live = batch_host_live<0, L>(it, key, valid, bact0, sub);
+        else if (it.width == 4) live = batch_host_live<4, L>(it, key, valid, bact0, sub);
         else if (it.width == 8) live = batch_host_live<8, L>(it, key, valid, bact0, sub);
         else live = batch_host_live<16, L>(it, key, valid, bact0, sub);
         if (valid && sub == 0) {

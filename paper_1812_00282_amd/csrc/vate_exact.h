@@ -97,6 +97,48 @@ __global__ void __launch_bounds__(256) k_init_x(Geo G, uint32_t *__restrict__ po
     }
 }
 
+// Census of group gi and its activity bitmap word: distances below k are
+// counted into hist (LDS) when given, else into the census.
+__device__ __forceinline__ void census_group_x(const Geo &G, const uint32_t *__restrict__ pool32, uint64_t gi,
+                                               uint32_t bact0, uint32_t *hist, unsigned long long *census,
+                                               uint8_t *__restrict__ bitmap)
+{
+    const uint32_t inact = inactive_value(G);
+    uint32_t vals[32];
+    read_group(pool32 + gi * G.wb, G.wb, vals);
+    const uint64_t p0 = gi * 32;
+    uint32_t bid0 = 0, act0 = 0;
+    uint64_t next = 0;
+    if (G.fast_blocks && !G.dr) {
+        bid0 = block_of(G, (uint32_t)p0);
+        act0 = block_act(G, bact0, bid0);
+        next = block_start(G, bid0 + 1);
+    }
+    uint32_t bits = 0;
+#pragma unroll
+    for (int e = 0; e < 32; ++e) {
+        const uint32_t val = vals[e];
+        if (val == inact) continue;
+        uint32_t d;
+        if (G.dr) {
+            d = val;
+        } else {
+            uint32_t act;
+            if (G.fast_blocks)
+                act = p0 + e < next ? act0 : block_act(G, bact0, bid0 + 1);
+            else
+                act = block_act(G, bact0, block_of(G, (uint32_t)(p0 + e)));
+            d = at_dist(G, act, val);
+        }
+        if (d < G.k) {
+            bits |= 1u << e;
+            if (hist) atomicAdd(&hist[d], 1u);
+            else atomicAdd(&census[d], 1ull);
+        }
+    }
+    reinterpret_cast<uint32_t *>(bitmap)[gi] = bits;
+}
+
 // Census and activity bitmap (one bitmap word per group).
 __global__ void __launch_bounds__(256) k_census_x(Geo G, const uint32_t *__restrict__ pool32, uint64_t ngroups,
                                                   DevState *__restrict__ st, uint8_t *__restrict__ bitmap)
@@ -106,43 +148,10 @@ __global__ void __launch_bounds__(256) k_census_x(Geo G, const uint32_t *__restr
     if (lds)
         for (uint32_t d = threadIdx.x; d < G.k; d += blockDim.x) hist[d] = 0;
     __syncthreads();
-    const uint32_t bact0 = st->bact0, inact = inactive_value(G);
+    const uint32_t bact0 = st->bact0;
     for (uint64_t gi = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; gi < ngroups;
-         gi += (uint64_t)gridDim.x * blockDim.x) {
-        uint32_t vals[32];
-        read_group(pool32 + gi * G.wb, G.wb, vals);
-        const uint64_t p0 = gi * 32;
-        uint32_t bid0 = 0, act0 = 0;
-        uint64_t next = 0;
-        if (G.fast_blocks && !G.dr) {
-            bid0 = block_of(G, (uint32_t)p0);
-            act0 = block_act(G, bact0, bid0);
-            next = block_start(G, bid0 + 1);
-        }
-        uint32_t bits = 0;
-#pragma unroll
-        for (int e = 0; e < 32; ++e) {
-            const uint32_t val = vals[e];
-            if (val == inact) continue;
-            uint32_t d;
-            if (G.dr) {
-                d = val;
-            } else {
-                uint32_t act;
-                if (G.fast_blocks)
-                    act = p0 + e < next ? act0 : block_act(G, bact0, bid0 + 1);
-                else
-                    act = block_act(G, bact0, block_of(G, (uint32_t)(p0 + e)));
-                d = at_dist(G, act, val);
-            }
-            if (d < G.k) {
-                bits |= 1u << e;
-                if (lds) atomicAdd(&hist[d], 1u);
-                else atomicAdd(&census_of(st)[d], 1ull);
-            }
-        }
-        reinterpret_cast<uint32_t *>(bitmap)[gi] = bits;
-    }
+         gi += (uint64_t)gridDim.x * blockDim.x)
+        census_group_x(G, pool32, gi, bact0, lds ? hist : nullptr, census_of(st), bitmap);
     __syncthreads();
     if (lds)
         for (uint32_t d = threadIdx.x; d < G.k; d += blockDim.x)
@@ -152,11 +161,9 @@ __global__ void __launch_bounds__(256) k_census_x(Geo G, const uint32_t *__restr
 // Alg. 3 on the two blocks whose ACT is 0 or k; thread j < max_groups takes
 // a group of the first block, the rest groups of the second (a group in both
 // ranges is handled once, by the first).
-__global__ void __launch_bounds__(256) k_preserve_x(Geo G, uint32_t *__restrict__ pool32,
-                                                    const DevState *__restrict__ st, uint64_t max_groups)
+__device__ __forceinline__ void preserve_group_x(const Geo &G, uint32_t *__restrict__ pool32, uint32_t bact0,
+                                                 uint64_t j, uint64_t max_groups)
 {
-    const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t bact0 = st->bact0;
     const uint32_t i0 = bact0 == 0 ? 0 : G.twok - bact0;                        // (BACT^0 + i0) mod 2k == 0
     const uint32_t i1 = bact0 <= G.k ? G.k - bact0 : G.twok + G.k - bact0;      // == k
     const uint64_t s0 = block_start(G, i0), e0 = block_start(G, i0 + 1);
@@ -191,21 +198,31 @@ __global__ void __launch_bounds__(256) k_preserve_x(Geo G, uint32_t *__restrict_
     if (changed) write_group(words, G.wb, vals);
 }
 
-// DR maintenance: every counter grows by one, saturating at k.
+__global__ void __launch_bounds__(256) k_preserve_x(Geo G, uint32_t *__restrict__ pool32,
+                                                    const DevState *__restrict__ st, uint64_t max_groups)
+{
+    preserve_group_x(G, pool32, st->bact0, (uint64_t)blockIdx.x * blockDim.x + threadIdx.x, max_groups);
+}
+
+// DR maintenance: every counter of group gi grows by one, saturating at k.
+__device__ __forceinline__ void dr_maintain_group_x(const Geo &G, uint32_t *__restrict__ pool32, uint64_t gi)
+{
+    uint32_t *words = pool32 + gi * G.wb;
+    uint32_t vals[32];
+    read_group(words, G.wb, vals);
+    bool changed = false;
+#pragma unroll
+    for (int e = 0; e < 32; ++e)
+        if (vals[e] < G.k) {
+            ++vals[e];
+            changed = true;
+        }
+    if (changed) write_group(words, G.wb, vals);
+}
+
 __global__ void __launch_bounds__(256) k_dr_maintain_x(Geo G, uint32_t *__restrict__ pool32, uint64_t ngroups)
 {
     for (uint64_t gi = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; gi < ngroups;
-         gi += (uint64_t)gridDim.x * blockDim.x) {
-        uint32_t *words = pool32 + gi * G.wb;
-        uint32_t vals[32];
-        read_group(words, G.wb, vals);
-        bool changed = false;
-#pragma unroll
-        for (int e = 0; e < 32; ++e)
-            if (vals[e] < G.k) {
-                ++vals[e];
-                changed = true;
-            }
-        if (changed) write_group(words, G.wb, vals);
-    }
+         gi += (uint64_t)gridDim.x * blockDim.x)
+        dr_maintain_group_x(G, pool32, gi);
 }

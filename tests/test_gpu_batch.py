@@ -67,6 +67,48 @@ def test_batch_matches_oracle():
                 assert np.all(np.abs(e - r_est) <= _tol(r_est, r.g)), (t, i)
 
 
+EXACT = [Config(12, 3, 3, 64, 0, 21, 22), Config(13, 7, 60, 128, 0, 23, 24), Config(11, 5, 12, 32, 1, 25, 26),
+         Config(14, 10, 300, 256, 0, 27, 28), Config(12, 6, 60, 64, 0, 29, 30, counter=1),
+         Config(13, 8, 20, 64, 0, 31, 32), Config(10, 9, 9, 16, 0, 33, 34, counter=1)]
+
+
+def test_batch_exact_widths_match_oracle():
+    """Exact-width pools (3, 5, 6, 7, 9 and 10 bits; AT and DR counters; both
+    block partitions) batched with a byte pool: every member's pool, clock,
+    census, live counts and estimates against its oracle twin after every
+    third slice, over more than 2k slices for the k = 3..60 members."""
+    rng = np.random.default_rng(5)
+    hosts = [rng.integers(0, 2**32, size=int(rng.integers(50, 400)), dtype=np.uint64).astype(np.uint32)
+             for _ in EXACT]
+    sks = [Sketch(c) for c in EXACT]
+    refs = [OracleSketch(c.log2_pool, c.width, c.k, c.g, c.seed_a, c.seed_b, c.partition, c.counter)
+            for c in EXACT]
+    b = Batch(sks, [6000] * len(EXACT), hosts)
+    n_slices = 125
+    for t in range(n_slices):
+        slices = [_rand_slice(rng, h, 0 if (t + i) % 11 == 10 else int(rng.integers(1, 6000)))
+                  for i, h in enumerate(hosts)]
+        b.load(slices)
+        b.slice()
+        for r, sl in zip(refs, slices):
+            r.ingest(sl)
+            r.close_slice()
+        if t % 3 == 2 or t == n_slices - 1:
+            b.synchronize()
+            for i, (sk, r) in enumerate(zip(sks, refs)):
+                _check_oracle(sk, b.est[i], b.live[i], r, hosts[i], np.arange(hosts[i].size), (t, i))
+
+
+def test_batch_exact_widths_graph_replay():
+    """Exact-width members under graph replay: every slice bit-exact with the
+    oracle twins and the standalone GPU twins."""
+    members = [streams.BatchMember(c.log2_pool, c.width, c.k, c.g, 200 + 37 * i, 700 + i)
+               for i, c in enumerate(EXACT) if c.counter == 0]
+    counts = lambda s: streams.batch_packet_counts(8, len(members), s, lo=3.0, hi=3.7)
+    timing, _ = _run_pair(members, 10, counts, graph=True)
+    assert len(timing["replay"]) == 9
+
+
 def _members_small():
     ms = streams.batch_members(seed=4, pool_range=(14, 18), host_shift=6)
     return ms
