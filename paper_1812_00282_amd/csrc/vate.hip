@@ -457,13 +457,15 @@ __global__ void __launch_bounds__(256) k_census(Geo G, const uint4 *__restrict__
 // chunks one each and leave each chunk's bits in its staging slot, and the
 // chunk's own lane picks them up; all-inactive chunks have zero bits.
 //
-// The rounds in which every lane's chunks lie inside the pool are software
-// pipelined: a round's loads are issued before the previous round is tested,
-// and its bitmap stores (a fixed number per lane) after, so the wait for the
-// loads never covers a store that is still in flight.  The remaining rounds
-// (at most one per thread) are guarded.
+// A lane takes U consecutive chunks per round (64 contiguous bytes, a
+// wavefront 4 KiB) and stores their 16-bit bitmap words as one 8-byte
+// store.  The rounds in which every lane's chunks lie inside the pool are
+// software pipelined: a round's loads are issued before the previous round
+// is tested, and its bitmap store after, so the wait for the loads never
+// covers a store that is still in flight.  The remaining round (at most
+// one) is guarded.
 constexpr uint32_t kCensus8Bins = 256;
-constexpr int kCensus8U = 4;   // chunks per lane and round
+constexpr int kCensus8U = 4;   // consecutive chunks per lane and round
 
 struct Census8Lds {
     uint32_t hist[kCensus8Bins];
@@ -471,10 +473,9 @@ struct Census8Lds {
     uint16_t c[4][64 * kCensus8U];    // staged chunk's (u * 64 + lane), then its bits
 };
 
-// One round of U chunks per lane (chunk u of this lane is c0 + u * stride):
-// bits[u] = the activity bits of chunk u.
-__device__ __forceinline__ void census8_round(const Geo &G, const uint4 (&v)[kCensus8U], uint64_t c0, uint64_t stride,
-                                              uint32_t bact0, uint32_t pat, Census8Lds &L, uint32_t (&bits)[kCensus8U],
+// One round: chunk u of this lane is c0 + u; bits[u] = its activity bits.
+__device__ __forceinline__ void census8_round(const Geo &G, const uint4 (&v)[kCensus8U], uint64_t c0, uint32_t bact0,
+                                              uint32_t pat, Census8Lds &L, uint32_t (&bits)[kCensus8U],
                                               unsigned long long *census)
 {
     constexpr int U = kCensus8U;
@@ -495,10 +496,10 @@ __device__ __forceinline__ void census8_round(const Geo &G, const uint4 (&v)[kCe
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const uint64_t wbase = c0 - lane;
+    const uint64_t wbase = c0 - (uint64_t)U * lane;     // the wavefront's first chunk
     for (uint32_t i = lane; i < n; i += 64) {
         const uint32_t code = L.c[wv][i];
-        const uint64_t ch = wbase + (code & 63u) + (uint64_t)(code >> 6) * stride;
+        const uint64_t ch = wbase + (uint64_t)U * (code & 63u) + (code >> 6);
         L.c[wv][i] = (uint16_t)census_chunk_fast<8>(G, L.v[wv][i], ch, bact0, pat, L.hist, census);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -516,24 +517,25 @@ __global__ void __launch_bounds__(256) k_census8(Geo G, const uint4 *__restrict_
                                                  unsigned long long *__restrict__ copies)
 {
     constexpr int U = kCensus8U;
+    static_assert(U == 4, "one 8-byte bitmap store per lane and round");
     __shared__ Census8Lds L;
     for (uint32_t d = threadIdx.x; d < G.k; d += blockDim.x) L.hist[d] = 0;
     __syncthreads();
     const uint32_t bact0 = st->bact0;
     const uint32_t pat = replicate<8>(inactive_value(G));
     const uint32_t lane = threadIdx.x & 63u;
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x, step = U * stride;
+    const uint64_t step = (uint64_t)U * gridDim.x * blockDim.x;     // chunks per round
     uint16_t *bm16 = reinterpret_cast<uint16_t *>(bitmap);
-    uint64_t c0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint64_t c0 = (uint64_t)U * (blockIdx.x * blockDim.x + threadIdx.x);
     uint32_t bits[U];
     const uint64_t full = nchunks / step;      // rounds with every chunk inside the pool
     if (full > 0) {
         uint4 v[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) v[u] = pool4[c0 + u * stride];
+        for (int u = 0; u < U; ++u) v[u] = pool4[c0 + u];
         // The first round's chunks are waited for here, so that the loop
         // entry leaves no load in flight that the loop head would wait for
-        // (a wait there would also cover the previous round's stores).
+        // (a wait there would also cover the previous round's store).
 #pragma unroll
         for (int u = 0; u < U; ++u) asm volatile("" ::"v"(v[u].x), "v"(v[u].y), "v"(v[u].z), "v"(v[u].w));
         for (uint64_t r = 0; r < full; ++r, c0 += step) {
@@ -541,25 +543,21 @@ __global__ void __launch_bounds__(256) k_census8(Geo G, const uint4 *__restrict_
             const uint64_t nx = r + 1 < full ? c0 + step : c0;
             uint4 w[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) w[u] = pool4[nx + u * stride];
-            census8_round(G, v, c0, stride, bact0, pat, L, bits, census_of(st));
-#pragma unroll
-            for (int u = 0; u < U; ++u) bm16[c0 + u * stride] = (uint16_t)bits[u];
+            for (int u = 0; u < U; ++u) w[u] = pool4[nx + u];
+            census8_round(G, v, c0, bact0, pat, L, bits, census_of(st));
+            *reinterpret_cast<uint2 *>(bm16 + c0) = make_uint2(bits[0] | bits[1] << 16, bits[2] | bits[3] << 16);
 #pragma unroll
             for (int u = 0; u < U; ++u) v[u] = w[u];
         }
     }
-    for (; c0 - lane < nchunks; c0 += step) {
+    if (c0 - (uint64_t)U * lane < nchunks) {   // the guarded last round (uniform per wavefront)
         uint4 v[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const uint64_t ch = c0 + u * stride;
-            v[u] = ch < nchunks ? pool4[ch] : make_uint4(pat, pat, pat, pat);
-        }
-        census8_round(G, v, c0, stride, bact0, pat, L, bits, census_of(st));
+        for (int u = 0; u < U; ++u) v[u] = c0 + u < nchunks ? pool4[c0 + u] : make_uint4(pat, pat, pat, pat);
+        census8_round(G, v, c0, bact0, pat, L, bits, census_of(st));
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            if (c0 + u * stride < nchunks) bm16[c0 + u * stride] = (uint16_t)bits[u];
+            if (c0 + u < nchunks) bm16[c0 + u] = (uint16_t)bits[u];
     }
     __syncthreads();
     // Flush into copy blockIdx mod kCensusCopies (k_census_fold adds the
@@ -1173,6 +1171,8 @@ static bool part_geo(const vate_sketch *s, uint64_t n, PartGeo *out)
     p.vats = (uint32_t)hosts * G.g;
     p.cap = (uint32_t)((p.vats + 3ull * ns + 3) & ~3ull);
     p.region = (p.cap + 63u) & ~63u;
+    // the lookup indexes the entries' 16-byte chunks with 32-bit integers
+    if ((uint64_t)p.n_sub * (p.region / 4u) >= (1ull << 32)) return false;
     p.dq = kRunThreads / G.g;
     p.dr = kRunThreads % G.g;
     p.fast = G.a >= (1ull << sl) ? 1u : 0u;

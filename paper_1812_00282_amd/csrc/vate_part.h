@@ -406,6 +406,17 @@ __global__ void __launch_bounds__(kRunThreads) k_run_lookup(Geo G, PartGeo PG, c
     const uint32_t rq = PG.region / 4;
     constexpr uint32_t kPass = 64u * kLookU;
     uint32_t *cnt = rcnt + 64u * wv;
+    // A lane's chunks of a pass and their runs.  A chunk past the end of the
+    // flat list keeps the entries it held before (the padding sentinel at
+    // first, every offset in range of the slice's bits); its bits are masked.
+    uint4 e4[kLookU];
+    uint32_t jr[kLookU];
+#pragma unroll
+    for (uint32_t q = 0; q < kLookU; ++q) {
+        const uint32_t pad = 1u << sl;
+        e4[q] = make_uint4(pad, pad, pad, pad);
+        jr[q] = 0;
+    }
     // A wavefront takes windows of 64 subgroups (lane r: run r of the
     // window), kRunThreads subgroups apart.  The window's runs in this slice
     // are one flat list of chunks (run after run), read in passes of kLookU
@@ -428,30 +439,27 @@ __global__ void __launch_bounds__(kRunThreads) k_run_lookup(Geo G, PartGeo PG, c
         }
         const uint32_t Fv = incl - len;                         // run r's first chunk in the flat list
         const uint32_t Ftot = __builtin_amdgcn_readlane(incl, 63);
+        // chunk i of the flat list, in run r, is chunk Bv + i of the entries
+        // (mod 2^32; the planner keeps every chunk index below 2^32)
+        const uint32_t Bv = (s0 + lane) * rq + Sv - Fv;
         for (uint32_t base = 0; base < Ftot; base += kPass) {
-            uint4 e4[kLookU];
-            uint32_t jr[kLookU];
 #pragma unroll
             for (uint32_t q = 0; q < kLookU; ++q) {
                 const uint32_t i0 = base + 64u * q, i = i0 + lane;
-                const uint32_t pad = 1u << sl;
-                e4[q] = make_uint4(pad, pad, pad, pad);
-                jr[q] = 0;
                 if (i0 < Ftot) {
                     // run of chunk i: the last r with F_r <= i (F is nondecreasing,
                     // and an empty run shares its F with the next)
                     const uint32_t last = min(i0 + 63u, Ftot - 1u);
                     const uint32_t jb = (uint32_t)__popcll(__ballot(Fv <= i0)) - 1u;
                     const uint32_t je = (uint32_t)__popcll(__ballot(Fv <= last)) - 1u;
-                    uint32_t j = jb;
-                    uint32_t Fj = __builtin_amdgcn_readlane(Fv, jb), Sj = __builtin_amdgcn_readlane(Sv, jb);
+                    uint32_t j = jb, Bj = __builtin_amdgcn_readlane(Bv, jb);
                     for (uint32_t jj = jb + 1; jj <= je; ++jj) {
                         const uint32_t f = __builtin_amdgcn_readlane(Fv, jj);
-                        const uint32_t sj = __builtin_amdgcn_readlane(Sv, jj);
-                        if (i >= f) j = jj, Fj = f, Sj = sj;
+                        const uint32_t bj = __builtin_amdgcn_readlane(Bv, jj);
+                        if (i >= f) j = jj, Bj = bj;
                     }
                     jr[q] = j;
-                    if (i < Ftot) e4[q] = ent4[(size_t)(s0 + j) * rq + Sj + (i - Fj)];
+                    if (i < Ftot) e4[q] = ent4[Bj + i];
                 }
             }
             // live bits (CheckAT for window k); a padding entry reads the
@@ -464,6 +472,12 @@ __global__ void __launch_bounds__(kRunThreads) k_run_lookup(Geo G, PartGeo PG, c
                     const uint32_t o = comp4(e4[q], m) & omask;
                     M |= __builtin_amdgcn_ubfe(bm[o >> 5], o, 1u) << (4u * q + m);   // bit o mod 32
                 }
+            // chunks past the list's end hold entries of an earlier pass
+            if (base + kPass > Ftot) {
+#pragma unroll
+                for (uint32_t q = 0; q < kLookU; ++q)
+                    if (base + 64u * q + lane >= Ftot) M &= ~(0xFu << (4u * q));
+            }
             // the live entries, up to four per lane per round (every lane
             // takes part in the shuffles)
             while (__ballot(M != 0)) {
