@@ -549,8 +549,11 @@ __device__ __forceinline__ uint32_t learned16(const Geo &G, float occupancy, con
     // one ballot per row says whether the host is outside the envelope.
     uint32_t outside = mlp::env_geometry_off(P, G.k, G.g, G.c, G.wb) ? 0xFFFFu : 0u;
     const mlp::EnvRange rng = mlp::env_range(P, l);     // this lane's feature in every row
+    // ln(max(closed form, 1)) of host l mod 16, once per lane
+    const float lnc = logf(fmaxf(cf16[l & 15], 1.0f));
     for (int e = l; e < 16 * VATE_MLP_FEATURES; e += 64) {
-        const int m = e >> 6, f = e & 63;
+        const int m = e >> 6, f = e & 63;     // m is the same in every lane
+        const float lnm = __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(lnc), m));
         float x = 0.f;
         if ((uint32_t)m < n16) {
             if (f < (int)G.k)
@@ -561,7 +564,7 @@ __device__ __forceinline__ uint32_t learned16(const Geo &G, float occupancy, con
             else if (f == (int)G.k + 1)
                 x = occupancy;
             else if (f == (int)G.k + 2)
-                x = logf(fmaxf(cf16[m], 1.0f)) * 0.0625f;
+                x = lnm * 0.0625f;
         }
         const uint16_t xb = mlp::bf16_bits(x);
         xs[m * mlp::LDS_STRIDE + f] = xb;
@@ -570,7 +573,7 @@ __device__ __forceinline__ uint32_t learned16(const Geo &G, float occupancy, con
     __syncthreads();
     float r4[4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) r4[r] = logf(fmaxf(cf16[4 * q + r], 1.0f));
+    for (int r = 0; r < 4; ++r) r4[r] = __shfl(lnc, 4 * q + r, 64);
     mlp::f32x4 z1[4], z2[4];
     float a2v[4][4], o4[4];
     mlp::forward16(P, xs, a1, r4, z1, z2, a2v, o4);
