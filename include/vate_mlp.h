@@ -3,7 +3,7 @@
  *
  * Not part of the paper: a small network that reads a host's sketch state
  * and stands in for Eq. 11's closed form, which stays as its fallback and as
- * the judge of its error.  Features of a host, for a sketch with window k
+ * the yardstick of its error.  Features of a host, for a sketch with window k
  * (k + 3 <= 64), all at window k:
  *     x[d]   = hist[d] / g      d < k   (VATs at distance d, Eq. 5)
  *     x[k]   = live / g                 (active VATs)
