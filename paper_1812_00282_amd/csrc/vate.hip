@@ -1035,7 +1035,7 @@ static void launch_census(vate_sketch *s, hipStream_t st)
     } else {
         uint64_t nch = s->pool_bytes / 16;
         if (W == 8 && s->G.k <= kCensus8Bins) {
-            k_census8<<<grid_for(nch, 256 * kCensus8U, 2048), 256, 0, st>>>(
+            k_census8<<<grid_for(nch, 256 * kCensus8U, 4096), 256, 0, st>>>(
                 s->G, reinterpret_cast<const uint4 *>(s->pool), nch, s->st, s->bitmap, s->copies);
             k_census_fold<<<1, 256, 0, st>>>(s->G, s->st, s->copies);
         } else {

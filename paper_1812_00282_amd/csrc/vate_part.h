@@ -35,7 +35,8 @@
 //  k_run_finalize a few subgroups per workgroup.  Reads the live results of
 //                 their runs (a subgroup's cells are contiguous, so mostly
 //                 whole lines), builds each host's distance histogram in LDS
-//                 (the inactive bin k is g minus the rest) and forms Eq. 11 for
+//                 (the inactive bin k, g minus the rest, only for the
+//                 histogram output) and forms Eq. 11 for
 //                 k', several windows, or the learned estimate (the network
 //                 fed from the LDS histograms, 16 hosts per wavefront).
 //
@@ -646,19 +647,21 @@ __global__ void __launch_bounds__(kFinThreads, 5) k_run_finalize(Geo G, PartGeo 
         }
     }
     __syncthreads();
-    for (uint32_t h = t; h < nh; h += kFinThreads) {   // bin k = g - (bins 0 .. k-1)
-        uint32_t *row = hist + h * rowp;
-        uint32_t live = 0;
-        for (uint32_t j = 0; j < G.k / 2; ++j) live += (row[j] & 0xFFFFu) + (row[j] >> 16);
-        const uint32_t w = G.k >> 1;
-        if (G.k & 1u) {
-            live += row[w] & 0xFFFFu;
-            row[w] = (row[w] & 0xFFFFu) | ((G.g - live) << 16);
-        } else {
-            row[w] = G.g - live;
+    if (MODE == kFinClosedForm && hist_out) {   // only the histogram output has bin k
+        for (uint32_t h = t; h < nh; h += kFinThreads) {   // bin k = g - (bins 0 .. k-1)
+            uint32_t *row = hist + h * rowp;
+            uint32_t live = 0;
+            for (uint32_t j = 0; j < G.k / 2; ++j) live += (row[j] & 0xFFFFu) + (row[j] >> 16);
+            const uint32_t w = G.k >> 1;
+            if (G.k & 1u) {
+                live += row[w] & 0xFFFFu;
+                row[w] = (row[w] & 0xFFFFu) | ((G.g - live) << 16);
+            } else {
+                row[w] = G.g - live;
+            }
         }
+        __syncthreads();
     }
-    __syncthreads();
 
     if constexpr (MODE == kFinClosedForm) {
         const uint64_t active_pool = pool_active(st, kprime);
