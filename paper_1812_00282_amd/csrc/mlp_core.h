@@ -170,9 +170,21 @@ __device__ __forceinline__ void gemm16x64(RowA arow, RowB brow, f32x4 acc[4])
     }
 }
 
+// Orders a wavefront's LDS writes before its later LDS reads (lanes of one
+// wavefront; no other wavefront waits).
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Per-wavefront forward pass over 16 samples whose bf16 features are rows of
 // xs (16 rows, stride LDS_STRIDE).  Leaves z1, z2 (D layout), writes a1 rows
 // into a1s (stride LDS_STRIDE) and returns o for rows 4q .. 4q+3 in o4.
+// WG_SYNC: the layer-1 activations are published with a workgroup barrier
+// (callers that then read other wavefronts' rows), else with a wavefront one.
+template <bool WG_SYNC = true>
 __device__ __forceinline__ void forward16(const Packed *__restrict__ P, const uint16_t *xs, uint16_t *a1s,
                                           const float r4[4], f32x4 z1[4], f32x4 z2[4], float a2v[4][4],
                                           float o4[4])
@@ -188,7 +200,10 @@ __device__ __forceinline__ void forward16(const Packed *__restrict__ P, const ui
             a1s[(4 * q + r) * LDS_STRIDE + n] = bf16_bits(gelu(z1[nt][r]));
         }
     }
-    __syncthreads();
+    if constexpr (WG_SYNC)
+        __syncthreads();
+    else
+        wave_sync();
     gemm16x64([&](int m) { return a1s + m * LDS_STRIDE; }, [&](int n) { return P->W2b + n * HD; }, z2);
     float part[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll

@@ -535,7 +535,7 @@ __device__ __forceinline__ uint32_t hist_bin(const uint32_t *row, uint32_t d)
 // features from their packed histogram rows (LDS, stride rowp), live counts
 // and closed forms (LDS, 16 each), the network on the matrix cores, exp of
 // its output (the closed form where that is not finite) to est[0, n16).
-// Every wavefront of the workgroup calls it (the network has a barrier).
+// Each wavefront works on its own 16 rows and synchronizes only with itself.
 // Returns the hosts given the closed form (the same in every lane).
 __device__ __forceinline__ uint32_t learned16(const Geo &G, float occupancy, const uint32_t *rw, uint32_t rowp,
                                           uint32_t n16, const float *cf16, const uint32_t *live16, uint16_t *xs,
@@ -571,13 +571,13 @@ __device__ __forceinline__ uint32_t learned16(const Geo &G, float occupancy, con
         xs[m * mlp::LDS_STRIDE + f] = xb;
         if (__ballot(mlp::env_outside(rng, xb))) outside |= 1u << m;
     }
-    __syncthreads();
+    mlp::wave_sync();
     float r4[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) r4[r] = __shfl(lnc, 4 * q + r, 64);
     mlp::f32x4 z1[4], z2[4];
     float a2v[4][4], o4[4];
-    mlp::forward16(P, xs, a1, r4, z1, z2, a2v, o4);
+    mlp::forward16<false>(P, xs, a1, r4, z1, z2, a2v, o4);
     bool fell = false;
     if (c < 4) {
         const uint32_t m = 4 * q + c;
@@ -707,6 +707,7 @@ __global__ void __launch_bounds__(kFinThreads, 5) k_run_finalize(Geo G, PartGeo 
         const uint32_t w = t >> 6;
         __shared__ uint32_t fell_wg;      // the workgroup's fallback hosts (one counter atomic per workgroup)
         if (t == 0) fell_wg = 0;
+        __syncthreads();                  // (the loop below synchronizes wavefronts only with themselves)
         uint32_t fell_wave = 0;
         for (uint32_t base = 0; base < nh; base += kFinThreads / 4) {
             {   // live count and closed form of host base + t / 4, four threads a host
@@ -729,7 +730,7 @@ __global__ void __launch_bounds__(kFinThreads, 5) k_run_finalize(Geo G, PartGeo 
                     live_s[hh] = live;
                 }
             }
-            __syncthreads();
+            mlp::wave_sync();   // hosts 16 w .. 16 w + 15 are wavefront w's, here and below
             const uint32_t m0 = base + 16 * w;
             const uint32_t n16 = nh > m0 ? min(16u, nh - m0) : 0u;
             // Opaque per group, so the weight fragments are loaded where they
@@ -738,7 +739,7 @@ __global__ void __launch_bounds__(kFinThreads, 5) k_run_finalize(Geo G, PartGeo 
             asm volatile("" : "+s"(Pg));
             fell_wave += learned16(G, occupancy, hist + m0 * rowp, rowp, n16, cf_s + 16 * w, live_s + 16 * w,
                                    xs_all[w], xs_all[w], Pg, est + h0 + m0);
-            __syncthreads();
+            mlp::wave_sync();
         }
         if ((t & 63u) == 0 && fell_wave) atomicAdd(&fell_wg, fell_wave);
         __syncthreads();
