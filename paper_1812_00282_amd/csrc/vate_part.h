@@ -552,21 +552,26 @@ __device__ __forceinline__ uint32_t learned16(const Geo &G, float occupancy, con
     const mlp::EnvRange rng = mlp::env_range(P, l);     // this lane's feature in every row
     // ln(max(closed form, 1)) of host l mod 16, once per lane
     const float lnc = logf(fmaxf(cf16[l & 15], 1.0f));
-    for (int e = l; e < 16 * VATE_MLP_FEATURES; e += 64) {
-        const int m = e >> 6, f = e & 63;     // m is the same in every lane
+    // Lane f builds feature f of every row, branch-free: every lane reads a
+    // word of the row (the bins' word for f < k, a word of the row otherwise)
+    // and keeps what its feature needs; rows past n16 read row 0 and are
+    // zeroed.
+    const int f = l;
+    const bool f_hist = f < (int)G.k, f_live = f == (int)G.k;
+    const bool f_occ = f == (int)G.k + 1, f_ln = f == (int)G.k + 2;
+    const uint32_t hw = min((uint32_t)f >> 1, rowp - 1u), hs = ((uint32_t)f & 1u) << 4;
+    static_assert(VATE_MLP_FEATURES == 64, "one feature per lane");
+    for (uint32_t m = 0; m < 16; ++m) {
         const float lnm = __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(lnc), m));
-        float x = 0.f;
-        if ((uint32_t)m < n16) {
-            if (f < (int)G.k)
-                x = (float)hist_bin(rw + m * rowp, f);
-            else if (f == (int)G.k)
-                x = (float)live16[m];
-            if (f <= (int)G.k) x = g_pow2 ? x * inv_g : x / fg;
-            else if (f == (int)G.k + 1)
-                x = occupancy;
-            else if (f == (int)G.k + 2)
-                x = lnm * 0.0625f;
-        }
+        const bool row_ok = m < n16;
+        const uint32_t mr = row_ok ? m : 0u;
+        uint32_t hv = rw[mr * rowp + hw], lv = live16[mr];
+        asm volatile("" : "+v"(hv), "+v"(lv));   // both read in every lane (no branches)
+        float x = (float)((hv >> hs) & 0xFFFFu);
+        x = f_hist ? x : (f_live ? (float)lv : 0.f);
+        x = g_pow2 ? x * inv_g : x / fg;
+        x = f_occ ? occupancy : (f_ln ? lnm * 0.0625f : x);
+        if (!row_ok) x = 0.f;
         const uint16_t xb = mlp::bf16_bits(x);
         xs[m * mlp::LDS_STRIDE + f] = xb;
         if (__ballot(mlp::env_outside(rng, xb))) outside |= 1u << m;
