@@ -738,10 +738,13 @@ __global__ void __launch_bounds__(kFinThreads, 5) k_run_finalize(Geo G, PartGeo 
             mlp::wave_sync();   // hosts 16 w .. 16 w + 15 are wavefront w's, here and below
             const uint32_t m0 = base + 16 * w;
             const uint32_t n16 = nh > m0 ? min(16u, nh - m0) : 0u;
-            // Opaque per group, so the weight fragments are loaded where they
-            // are used rather than hoisted out of the loop into registers.
-            const mlp::Packed *Pg = P;
-            asm volatile("" : "+s"(Pg));
+            // An opaque zero offset per group, so the weight fragments are
+            // loaded where they are used rather than hoisted out of the loop
+            // into registers (the pointer stays a global one, so the loads
+            // are global loads that wait only on the vector-memory counter).
+            uint32_t zero = 0;
+            asm volatile("" : "+s"(zero));
+            const mlp::Packed *Pg = P + zero;
             fell_wave += learned16(G, occupancy, hist + m0 * rowp, rowp, n16, cf_s + 16 * w, live_s + 16 * w,
                                    xs_all[w], xs_all[w], Pg, est + h0 + m0);
             mlp::wave_sync();
