@@ -633,11 +633,14 @@ __global__ void __launch_bounds__(kFinThreads, 5) k_run_finalize(Geo G, PartGeo 
         for (uint32_t r = t; r < nr; r += kFinThreads) {
             const uint32_t sg = r / ns, b = r - sg * ns;
             const uint32_t *trow = table + (size_t)(s0 + sg) * (ns + 1);
+            // the run's head cell is read with its table cells (one round
+            // trip; a run without live results reads a cell it ignores)
             const uint32_t c = trow[b], start = c & 0xFFFFu;
-            const uint32_t cnt = min(c >> 16, 4u * ((trow[b + 1] & 0xFFFFu) - start));
-            if (cnt == 0) continue;
-            const uint32_t hrow = sg * PG.hosts;
             const uint4 w4 = heads4[(size_t)(s0 + sg) * ns + b];
+            uint32_t zero = 0;                 // an opaque zero: the count depends on the cell,
+            asm volatile("" : "+v"(zero));     // so the cell's load is issued before the count is used
+            const uint32_t cnt = min(c >> 16, 4u * ((trow[b + 1] & 0xFFFFu) - start)) + (w4.x & zero);
+            const uint32_t hrow = sg * PG.hosts;
 #pragma unroll
             for (uint32_t m = 0; m < 4; ++m) {
                 if (m >= cnt) break;
