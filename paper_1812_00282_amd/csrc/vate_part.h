@@ -537,9 +537,12 @@ __device__ __forceinline__ uint32_t hist_bin(const uint32_t *row, uint32_t d)
 // its output (the closed form where that is not finite) to est[0, n16).
 // Each wavefront works on its own 16 rows and synchronizes only with itself.
 // Returns the hosts given the closed form (the same in every lane).
+// geo_off: the envelope rules the network out for this sketch's geometry
+// (the same for every host; read once by the caller).
 __device__ __forceinline__ uint32_t learned16(const Geo &G, float occupancy, const uint32_t *rw, uint32_t rowp,
                                           uint32_t n16, const float *cf16, const uint32_t *live16, uint16_t *xs,
-                                          uint16_t *a1, const mlp::Packed *__restrict__ P, float *__restrict__ est)
+                                          uint16_t *a1, const mlp::Packed *__restrict__ P, float *__restrict__ est,
+                                          bool geo_off)
 {
     const int l = threadIdx.x & 63, q = l >> 4, c = l & 15;
     const float fg = (float)G.g;
@@ -548,10 +551,11 @@ __device__ __forceinline__ uint32_t learned16(const Geo &G, float occupancy, con
     const float inv_g = 1.0f / fg;
     // Row m (host m) is built by the whole wavefront, lane f = feature f, so
     // one ballot per row says whether the host is outside the envelope.
-    uint32_t outside = mlp::env_geometry_off(P, G.k, G.g, G.c, G.wb) ? 0xFFFFu : 0u;
+    uint32_t outside = geo_off ? 0xFFFFu : 0u;
     const mlp::EnvRange rng = mlp::env_range(P, l);     // this lane's feature in every row
-    // ln(max(closed form, 1)) of host l mod 16, once per lane
+    // ln(max(closed form, 1)) and the live count of host l mod 16, once per lane
     const float lnc = logf(fmaxf(cf16[l & 15], 1.0f));
+    const uint32_t lvl = live16[l & 15];
     // Lane f builds feature f of every row, branch-free: every lane reads a
     // word of the row (the bins' word for f < k, a word of the row otherwise)
     // and keeps what its feature needs; rows past n16 read row 0 and are
@@ -561,20 +565,27 @@ __device__ __forceinline__ uint32_t learned16(const Geo &G, float occupancy, con
     const bool f_occ = f == (int)G.k + 1, f_ln = f == (int)G.k + 2;
     const uint32_t hw = min((uint32_t)f >> 1, rowp - 1u), hs = ((uint32_t)f & 1u) << 4;
     static_assert(VATE_MLP_FEATURES == 64, "one feature per lane");
-    for (uint32_t m = 0; m < 16; ++m) {
-        const float lnm = __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(lnc), m));
-        const bool row_ok = m < n16;
-        const uint32_t mr = row_ok ? m : 0u;
-        uint32_t hv = rw[mr * rowp + hw], lv = live16[mr];
-        asm volatile("" : "+v"(hv), "+v"(lv));   // both read in every lane (no branches)
-        float x = (float)((hv >> hs) & 0xFFFFu);
-        x = f_hist ? x : (f_live ? (float)lv : 0.f);
-        x = g_pow2 ? x * inv_g : x / fg;
-        x = f_occ ? occupancy : (f_ln ? lnm * 0.0625f : x);
-        if (!row_ok) x = 0.f;
-        const uint16_t xb = mlp::bf16_bits(x);
-        xs[m * mlp::LDS_STRIDE + f] = xb;
-        if (__ballot(mlp::env_outside(rng, xb))) outside |= 1u << m;
+    // four rows at a time: their words are read together, in every lane
+#pragma unroll
+    for (uint32_t m0 = 0; m0 < 16; m0 += 4) {
+        uint32_t hv[4];
+#pragma unroll
+        for (uint32_t u = 0; u < 4; ++u) hv[u] = rw[(m0 + u < n16 ? m0 + u : 0u) * rowp + hw];
+        asm volatile("" : "+v"(hv[0]), "+v"(hv[1]), "+v"(hv[2]), "+v"(hv[3]));
+#pragma unroll
+        for (uint32_t u = 0; u < 4; ++u) {
+            const uint32_t m = m0 + u;
+            const float lnm = __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(lnc), m));
+            const uint32_t lv = __builtin_amdgcn_readlane(lvl, m);
+            float x = (float)((hv[u] >> hs) & 0xFFFFu);
+            x = f_hist ? x : (f_live ? (float)lv : 0.f);
+            x = g_pow2 ? x * inv_g : x / fg;
+            x = f_occ ? occupancy : (f_ln ? lnm * 0.0625f : x);
+            if (m >= n16) x = 0.f;
+            const uint16_t xb = mlp::bf16_bits(x);
+            xs[m * mlp::LDS_STRIDE + f] = xb;
+            if (__ballot(mlp::env_outside(rng, xb))) outside |= 1u << m;
+        }
     }
     mlp::wave_sync();
     float r4[4];
@@ -713,6 +724,7 @@ __global__ void __launch_bounds__(kFinThreads, 5) k_run_finalize(Geo G, PartGeo 
         const uint64_t active_pool = pool_active(st, G.k);
         const float occupancy = (float)active_pool / (float)G.N;
         const uint32_t w = t >> 6;
+        const bool geo_off = mlp::env_geometry_off(P, G.k, G.g, G.c, G.wb);
         __shared__ uint32_t fell_wg;      // the workgroup's fallback hosts (one counter atomic per workgroup)
         if (t == 0) fell_wg = 0;
         __syncthreads();                  // (the loop below synchronizes wavefronts only with themselves)
@@ -749,7 +761,7 @@ __global__ void __launch_bounds__(kFinThreads, 5) k_run_finalize(Geo G, PartGeo 
             asm volatile("" : "+s"(zero));
             const mlp::Packed *Pg = P + zero;
             fell_wave += learned16(G, occupancy, hist + m0 * rowp, rowp, n16, cf_s + 16 * w, live_s + 16 * w,
-                                   xs_all[w], xs_all[w], Pg, est + h0 + m0);
+                                   xs_all[w], xs_all[w], Pg, est + h0 + m0, geo_off);
             mlp::wave_sync();
         }
         if ((t & 63u) == 0 && fell_wave) atomicAdd(&fell_wg, fell_wave);
