@@ -271,6 +271,9 @@ __device__ __forceinline__ uint32_t comp4(const uint4 &v, uint32_t m)
     return m == 0 ? v.x : m == 1 ? v.y : m == 2 ? v.z : v.w;
 }
 
+constexpr uint32_t kBmLoads = 8;      // 16-byte bitmap loads in flight per thread
+constexpr uint32_t kDistWords = 8;    // bitmap words whose first live AT is loaded together
+
 // Rank support for the slice's activity bits in the lookup's LDS: the live
 // ATs before each superblock of 2048 ATs (32 bits) and before each block of
 // 256 ATs within its superblock (16 bits); a live AT's rank is those plus
@@ -323,8 +326,30 @@ __global__ void __launch_bounds__(kRunThreads) k_run_lookup(Geo G, PartGeo PG, c
     const uint32_t s_lo = part * PG.span, s_hi = min(PG.n_sub, s_lo + PG.span);
     const uint32_t t = threadIdx.x, lane = t & 63u, wv = t >> 6;
     {
+        // From 2^7 ATs a slice's words are whole 16-byte groups (16-byte
+        // aligned): a thread issues all its group loads before it stores any,
+        // so the slice's bits take one round trip rather than one per word.
         const uint32_t *src = bitmap + (size_t)b * nw;
-        for (uint32_t q = t; q < nwp; q += kRunThreads) {
+        const uint32_t nv = sl >= 7 ? nw / 4u : 0u;
+        const uint4 *src4 = reinterpret_cast<const uint4 *>(src);
+        uint4 *bm4 = reinterpret_cast<uint4 *>(bm);
+        for (uint32_t q0 = t; q0 < nv; q0 += kBmLoads * kRunThreads) {
+            uint4 v[kBmLoads];
+#pragma unroll
+            for (uint32_t u = 0; u < kBmLoads; ++u) {
+                const uint32_t q = q0 + u * kRunThreads;
+                v[u] = src4[q < nv ? q : q0];     // a group past the end reloads q0 and is not stored
+            }
+            // every load is used here, so none is sunk into its store's branch
+#pragma unroll
+            for (uint32_t u = 0; u < kBmLoads; ++u) asm volatile("" ::"v"(v[u].x), "v"(v[u].y), "v"(v[u].z), "v"(v[u].w));
+#pragma unroll
+            for (uint32_t u = 0; u < kBmLoads; ++u) {
+                const uint32_t q = q0 + u * kRunThreads;
+                if (q < nv) bm4[q] = v[u];
+            }
+        }
+        for (uint32_t q = 4u * nv + t; q < nwp; q += kRunThreads) {
             uint32_t v = q < nw ? src[q] : 0u;
             if (sl < 5 && q == 0) v &= (1u << (1u << sl)) - 1u;   // bits past the pool: the sentinel among them
             bm[q] = v;
@@ -369,8 +394,7 @@ __global__ void __launch_bounds__(kRunThreads) k_run_lookup(Geo G, PartGeo PG, c
     }
     // Distance (Eq. 5) of a live AT at offset o of the slice, from the pool;
     // its bit says it is active for window k, so d < k.
-    auto dist_at = [&](uint32_t o) -> uint32_t {
-        const uint32_t v = load_at<W>(pool, first | o, G.wb);
+    auto dist_of = [&](uint32_t o, uint32_t v) -> uint32_t {
         if (v == inact) return G.k;
         uint32_t d;
         if (G.dr) {
@@ -381,21 +405,55 @@ __global__ void __launch_bounds__(kRunThreads) k_run_lookup(Geo G, PartGeo PG, c
         }
         return d < G.k ? d : G.k;
     };
+    auto dist_at = [&](uint32_t o) -> uint32_t { return dist_of(o, load_at<W>(pool, first | o, G.wb)); };
+    auto put_dist = [&](uint32_t r, uint32_t d) {
+        if (PG.dist16) dist16[r] = (uint16_t)d; else dist8[r] = (uint8_t)d;
+    };
     // The distances of the slice's live ATs, in slice order, when they fit
     // the LDS left over; otherwise each live entry reads its AT from the pool.
+    // A thread takes a contiguous range of words: one rank lookup for its
+    // first word, then running popcounts.  Words go kDistWords at a time;
+    // the AT of each word's first live bit is loaded for all of them at once
+    // (a word with no live bit loads the slice's first AT and drops it), and
+    // a word's further live bits (a few per cent of the words) one by one.
     const bool in_lds = live <= PG.dist_cap;
     __syncthreads();
     if (in_lds) {
-        for (uint32_t q = t; q < nw; q += kRunThreads) {
-            uint32_t bits = bm[q];
-            if (!bits) continue;
-            uint32_t r = live_rank(bm, sup, blk, 32u * q);
-            while (bits) {
-                const uint32_t x = __builtin_ctz(bits);
-                bits &= bits - 1u;
-                const uint32_t d = dist_at(32u * q + x);
-                if (PG.dist16) dist16[r] = (uint16_t)d; else dist8[r] = (uint8_t)d;
-                ++r;
+        const uint32_t per = (nw + kRunThreads - 1u) / kRunThreads;
+        const uint32_t q_lo = min(nw, t * per), q_hi = min(nw, q_lo + per);
+        uint32_t r = q_lo < q_hi ? live_rank(bm, sup, blk, 32u * q_lo) : 0u;
+        for (uint32_t q0 = q_lo; q0 < q_hi; q0 += kDistWords) {
+            uint32_t bits[kDistWords], v[kDistWords], rb[kDistWords];
+#pragma unroll
+            for (uint32_t u = 0; u < kDistWords; ++u) {
+                // q < q_hi + 7 <= nw + 7 stays inside the LDS block (the
+                // rank tables follow the bits); words past q_hi count as empty
+                const uint32_t q = q0 + u, w = bm[q];
+                bits[u] = q < q_hi ? w : 0u;
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < kDistWords; ++u) {
+                const uint32_t o = bits[u] ? 32u * (q0 + u) + (uint32_t)__builtin_ctz(bits[u]) : 0u;
+                v[u] = load_at<W>(pool, first | o, G.wb);
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < kDistWords; ++u) asm volatile("" : "+v"(v[u]));
+#pragma unroll
+            for (uint32_t u = 0; u < kDistWords; ++u) {
+                rb[u] = r;
+                r += (uint32_t)__popc(bits[u]);
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < kDistWords; ++u)
+                if (bits[u]) put_dist(rb[u], dist_of(32u * (q0 + u) + (uint32_t)__builtin_ctz(bits[u]), v[u]));
+#pragma unroll
+            for (uint32_t u = 0; u < kDistWords; ++u) {
+                uint32_t rest = bits[u] & (bits[u] - 1u), rr = rb[u] + 1u;
+                while (rest) {
+                    const uint32_t x = __builtin_ctz(rest);
+                    rest &= rest - 1u;
+                    put_dist(rr++, dist_at(32u * (q0 + u) + x));
+                }
             }
         }
     }
