@@ -667,6 +667,8 @@ __device__ __forceinline__ uint32_t learned16(const Geo &G, float occupancy, con
 // At least 5 wavefronts per SIMD: the network's registers would otherwise
 // hold the streaming pass to 4 (measured 0.64 against 0.58 ms on the 40G
 // workload; 6 would spill).
+constexpr uint32_t kFinRuns = 4;   // runs whose cells a finalize thread loads together
+
 template <int MODE>
 __global__ void __launch_bounds__(kFinThreads, 5) k_run_finalize(Geo G, PartGeo PG, const DevState *__restrict__ st,
                                                              uint32_t n, uint32_t kprime,
@@ -698,28 +700,46 @@ __global__ void __launch_bounds__(kFinThreads, 5) k_run_finalize(Geo G, PartGeo 
         // atomic; bin k (inactive) is not counted: it is g minus the others,
         // filled in below.  (A live count never exceeds the run's entries;
         // the clamp keeps every read inside them whatever the table holds.)
+        // A thread takes kFinRuns runs at a time: their table cells and head
+        // cells are all loaded before the first is counted (one round trip
+        // for the batch; a run past the end reloads the batch's first run's
+        // cells and is skipped, a run without live results ignores its head).
         const uint4 *heads4 = reinterpret_cast<const uint4 *>(heads);
-        for (uint32_t r = t; r < nr; r += kFinThreads) {
-            const uint32_t sg = r / ns, b = r - sg * ns;
-            const uint32_t *trow = table + (size_t)(s0 + sg) * (ns + 1);
-            // the run's head cell is read with its table cells (one round
-            // trip; a run without live results reads a cell it ignores)
-            const uint32_t c = trow[b], start = c & 0xFFFFu;
-            const uint4 w4 = heads4[(size_t)(s0 + sg) * ns + b];
-            uint32_t zero = 0;                 // an opaque zero: the count depends on the cell,
-            asm volatile("" : "+v"(zero));     // so the cell's load is issued before the count is used
-            const uint32_t cnt = min(c >> 16, 4u * ((trow[b + 1] & 0xFFFFu) - start)) + (w4.x & zero);
-            const uint32_t hrow = sg * PG.hosts;
+        for (uint32_t r0 = t; r0 < nr; r0 += kFinRuns * kFinThreads) {
+            uint32_t c[kFinRuns], c1[kFinRuns];
+            uint4 w4[kFinRuns];
 #pragma unroll
-            for (uint32_t m = 0; m < 4; ++m) {
-                if (m >= cnt) break;
-                const uint32_t v = comp4(w4, m), d = v & 0xFFFFu;
-                if (d < G.k) atomicAdd(&hist[(hrow + (v >> 16)) * rowp + (d >> 1)], 1u << ((d & 1u) << 4));
+            for (uint32_t u = 0; u < kFinRuns; ++u) {
+                const uint32_t r = r0 + u * kFinThreads < nr ? r0 + u * kFinThreads : r0;
+                const uint32_t sg = r / ns, b = r - sg * ns;
+                const uint32_t *trow = table + (size_t)(s0 + sg) * (ns + 1);
+                c[u] = trow[b];
+                c1[u] = trow[b + 1];
+                w4[u] = heads4[(size_t)(s0 + sg) * ns + b];
             }
-            const uint32_t *more = hits + (size_t)(s0 + sg) * PG.region + 4u * start;
-            for (uint32_t i = 4; i < cnt; ++i) {
-                const uint32_t v = more[i - 4u], d = v & 0xFFFFu;
-                if (d < G.k) atomicAdd(&hist[(hrow + (v >> 16)) * rowp + (d >> 1)], 1u << ((d & 1u) << 4));
+            // every load is used here, so none is sunk into its run's branch
+#pragma unroll
+            for (uint32_t u = 0; u < kFinRuns; ++u)
+                asm volatile("" ::"v"(c[u]), "v"(c1[u]), "v"(w4[u].x), "v"(w4[u].y), "v"(w4[u].z), "v"(w4[u].w));
+#pragma unroll
+            for (uint32_t u = 0; u < kFinRuns; ++u) {
+                const uint32_t r = r0 + u * kFinThreads;
+                if (r >= nr) break;
+                const uint32_t sg = r / ns;
+                const uint32_t start = c[u] & 0xFFFFu;
+                const uint32_t cnt = min(c[u] >> 16, 4u * ((c1[u] & 0xFFFFu) - start));
+                const uint32_t hrow = sg * PG.hosts;
+#pragma unroll
+                for (uint32_t m = 0; m < 4; ++m) {
+                    if (m >= cnt) break;
+                    const uint32_t v = comp4(w4[u], m), d = v & 0xFFFFu;
+                    if (d < G.k) atomicAdd(&hist[(hrow + (v >> 16)) * rowp + (d >> 1)], 1u << ((d & 1u) << 4));
+                }
+                const uint32_t *more = hits + (size_t)(s0 + sg) * PG.region + 4u * start;
+                for (uint32_t i = 4; i < cnt; ++i) {
+                    const uint32_t v = more[i - 4u], d = v & 0xFFFFu;
+                    if (d < G.k) atomicAdd(&hist[(hrow + (v >> 16)) * rowp + (d >> 1)], 1u << ((d & 1u) << 4));
+                }
             }
         }
     }
